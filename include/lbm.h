@@ -1,0 +1,200 @@
+/*
+ * lbm.h -- C ABI of the MinxEnt-LBM stream-and-collide library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the MinxEnt lattice Boltzmann method of T. L. Wilson,
+ * M. Pugh and F. Dawson, "Stabilization of the Lattice Boltzmann Method Using
+ * Information Theory" (arXiv:1801.03863): every fluid node replaces the BGK
+ * relaxation by one Newton-Raphson step that minimises the Kullback-Leibler
+ * divergence from the lattice weights subject to mass, momentum and relaxed
+ * stress constraints (Sec. IV.C-D), followed by streaming (Sec. II.A).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: LBM_OK (0) or a negative error code (LBM_E*).  A failed
+ *    call leaves no partial object behind; lbm_last_error() gives a message.
+ *  - Host arrays of macroscopic fields are row-major [y][x] (x fastest), one
+ *    double per node, nx*ny values (nx for D1Q3).  Batched calls take the
+ *    instances' arrays concatenated in instance order.
+ *  - D2Q9 populations are ordered rest, E, N, W, S, NE, NW, SW, SE: the
+ *    column order of the moment matrix T of Sec. IV.D (Table I lists the
+ *    same set with the rest velocity last).  D1Q3: rest, +1, -1.
+ *  - Device memory handed in by the caller stays owned by the caller; the
+ *    library never frees it.  A NULL workspace makes the library allocate
+ *    (and later free) its own.
+ *  - hip_stream is a hipStream_t passed as void*; NULL means the default
+ *    stream.  All device work of a context is ordered on that stream.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ *  - Instability (a negative or non-finite post-collision population at a
+ *    fluid node, Sec. IV.G) is not an error return: it sets a sticky status
+ *    bit read by lbm_status(), so lbm_step() stays asynchronous.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+/* Error codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)   /* bad argument or parameter combination */
+#define LBM_ENOMEM (-2)   /* device or host allocation failed, or workspace too small */
+#define LBM_EHIP (-3)     /* a HIP runtime call failed; see lbm_last_error() */
+#define LBM_ENODEV (-4)   /* no usable gfx950 device */
+
+/* Lattices: D1Q3 and D2Q9 (Table I). */
+enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
+
+/* Collision rule of fluid nodes.  MINXENT4 is the paper's MinxEnt with five
+ * constraints and four free moments (Sec. IV.C-D); MINXENT2 adds the two
+ * constraints C5, C7 relaxed with tau2 (two free moments).  SRT is the BGK
+ * rule of Sec. II.B.1.  On D1Q3 every rule is SRT: with mass, momentum and
+ * the relaxed second moment fixed no moment is left to minimise over. */
+enum { LBM_MINXENT4 = 0, LBM_MINXENT2 = 1, LBM_SRT = 2 };
+
+/* Boundary kinds (Sec. IV.E): full-way bounce-back walls and an equilibrium
+ * moving wall.
+ *   PERIODIC: every axis wraps, every node is fluid.
+ *   TUBE:     walls at x = 0 and x = nx-1; y wraps (D2Q9).
+ *   CAVITY:   walls at x = 0, x = nx-1, y = 0; the top row y = ny-1,
+ *             corners included, is a lid held at the equilibrium of
+ *             (rho0, (u_lid, 0)).  D1Q3: walls at both ends.
+ *   BOX:      walls on every side. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_TUBE = 1, LBM_BC_CAVITY = 2, LBM_BC_BOX = 3 };
+
+/* Storage / arithmetic forms.
+ *   FP64:          populations stored and computed in double.
+ *   FP32_NEWTON64: populations stored in float, every node computed in
+ *                  double (moments, logarithms, Newton step, correction).
+ *   FP32:          stored and computed in float; the logarithms are taken of
+ *                  the small deviations from the weights (log1p), so the
+ *                  gradient does not cancel.
+ *   FP16DEV:       stored as binary16 deviations (f_i - W_i rho0) * 2^k,
+ *                  computed in float as FP32. */
+enum { LBM_FP64 = 0, LBM_FP32_NEWTON64 = 1, LBM_FP32 = 2, LBM_FP16DEV = 3 };
+
+typedef struct lbm_params {
+    int32_t lattice;    /* LBM_D1Q3 or LBM_D2Q9 */
+    int32_t collision;  /* LBM_MINXENT4, LBM_MINXENT2 or LBM_SRT */
+    int32_t bc;         /* LBM_BC_* */
+    int32_t precision;  /* LBM_FP64, LBM_FP32_NEWTON64, LBM_FP32, LBM_FP16DEV */
+    int32_t nx, ny;     /* nodes per axis, boundary nodes included; ny = 1 for D1Q3 */
+    int32_t fp16_exp;   /* FP16DEV scale exponent k (0 selects 16); ignored otherwise */
+    int32_t reserved;   /* must be 0 */
+    double tau;         /* relaxation time, > 1/2; nu = (2 tau - 1)/6 (Sec. IV.C) */
+    double tau2;        /* MINXENT2 only; <= 0 selects (8 tau - 1)/(2 tau - 1) (Sec. IV.C) */
+    double u_lid;       /* lid x-velocity for LBM_BC_CAVITY */
+    double rho0;        /* lid density, and the FP16DEV reference density */
+} lbm_params_t;
+
+typedef struct lbm_status {
+    uint32_t flags;      /* bit 0: UNSTABLE, bit 1: GUARDED (some node skipped its Newton step) */
+    int32_t reserved;
+    int64_t first_step;  /* step (0-based) of the first UNSTABLE event, -1 if none */
+    int64_t guarded;     /* node-steps whose Newton start point had a population <= 0 */
+} lbm_status_t;
+
+typedef struct lbm_ctx lbm_ctx_t;
+
+/* Bytes of device workspace a context for p needs: the two population
+ * buffers (2 * b * padded nodes * bytes per stored population).  Returns
+ * LBM_EINVAL for invalid parameters. */
+int lbm_workspace_bytes(const lbm_params_t *p, size_t *bytes);
+
+/* Create a context and set every node to the polynomial equilibrium of the
+ * given fields (Sec. IV.E, initial state); lid nodes start at the lid
+ * equilibrium.  rho, ux, uy: host arrays, nx*ny doubles each (uy ignored and
+ * may be NULL for D1Q3); read only during the call.  dev_workspace: caller
+ * device memory of ws_bytes >= lbm_workspace_bytes(), or NULL.  On success
+ * *out holds the new context; the device state is ready when the stream
+ * reaches this point. */
+int lbm_init(const lbm_params_t *p, const double *rho, const double *ux, const double *uy,
+             void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_ctx_t **out);
+
+/* Workspace bytes for a batch of n independent instances (each with its own
+ * size, tau, tau2, u_lid).  All instances share lattice, collision, bc and
+ * precision. */
+int lbm_workspace_bytes_batch(const lbm_params_t *p, int32_t n, size_t *bytes);
+
+/* Create a batched context: n instances advanced together by one launch per
+ * time step.  p: n parameter records; fields concatenated in instance order. */
+int lbm_init_batch(const lbm_params_t *p, int32_t n, const double *rho, const double *ux,
+                   const double *uy, void *dev_workspace, size_t ws_bytes, void *hip_stream,
+                   lbm_ctx_t **out);
+
+/* Enqueue nsteps time steps (collide and stream at every node) on the
+ * context's stream and return without waiting.  nsteps >= 0. */
+int lbm_step(lbm_ctx_t *ctx, int64_t nsteps);
+
+/* Replay time steps from a captured HIP graph of `chunk` steps (chunk >= 1;
+ * 0 turns graph replay off).  lbm_step() then enqueues nsteps / chunk graph
+ * launches plus the remainder as plain launches.  Results are bitwise equal
+ * to plain launches. */
+int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
+
+/* Time the candidate launch shapes of the fused kernel on this context's own
+ * buffers (the state is left unchanged) and keep the fastest.  Candidates
+ * produce bitwise identical results.  If cache_path is not NULL the choice is
+ * read from / appended to that text file, keyed by device, lattice,
+ * precision, collision, boundary and size.  *chosen (may be NULL) receives
+ * the index of the chosen shape. */
+int lbm_autotune(lbm_ctx_t *ctx, const char *cache_path, int32_t *chosen);
+
+/* Force a launch shape by index (0 = default); LBM_EINVAL if out of range. */
+int lbm_set_variant(lbm_ctx_t *ctx, int32_t variant);
+
+/* Number of launch shapes (for lbm_set_variant) and a short description. */
+int lbm_variant_count(const lbm_ctx_t *ctx);
+const char *lbm_variant_name(const lbm_ctx_t *ctx, int32_t variant);
+
+/* Write rho, ux, uy of the current state (Sec. II.A moments of the
+ * populations every node holds before its next collision) into host arrays
+ * of nx*ny doubles (concatenated over instances for a batch); any pointer may
+ * be NULL.  Synchronises the stream. */
+int lbm_moments(lbm_ctx_t *ctx, double *rho, double *ux, double *uy);
+
+/* Copy the current populations (the pre-collision state of every node) to
+ * host memory: b planes of nodes doubles each (instance-concatenated for a
+ * batch).  Slots fed from outside the lattice on boundary nodes hold
+ * unspecified values.  Synchronises. */
+int lbm_get_populations(lbm_ctx_t *ctx, double *f);
+
+/* Replace the state with host populations in the layout lbm_get_populations
+ * returns (checkpoint restore); resets nothing else.  Synchronises. */
+int lbm_set_populations(lbm_ctx_t *ctx, const double *f);
+
+/* Status of instance 0 (or the OR/sum over all instances of a batch).
+ * Synchronises. */
+int lbm_status(lbm_ctx_t *ctx, lbm_status_t *out);
+
+/* Per-instance status of a batch (n records).  Synchronises. */
+int lbm_status_batch(lbm_ctx_t *ctx, lbm_status_t *out, int32_t n);
+
+/* Clear the status of every instance (stream-ordered). */
+int lbm_reset_status(lbm_ctx_t *ctx);
+
+/* Steps taken so far, nodes per step, and algorithmic HBM bytes per step
+ * (every stored population read once and written once). */
+int lbm_info(const lbm_ctx_t *ctx, int64_t *steps_done, int64_t *nodes, int64_t *bytes_per_step);
+
+/* Destroy a context; NULL-safe; never frees caller memory.  Synchronises. */
+void lbm_free(lbm_ctx_t *ctx);
+
+/* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16) on
+ * hip_stream: a reference for achievable HBM bandwidth. */
+int lbm_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* Message of the last error on this thread, and the text of an error code. */
+const char *lbm_last_error(void);
+const char *lbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,297 @@
+// collide.hpp -- per-node collision rules of MinxEnt-LBM for gfx950, held
+// entirely in registers.
+//
+// Populations are indexed in the column order of the moment matrix T
+// (Sec. IV.D): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+//
+// MinxEnt4 (Sec. IV.C-D).  Mass, momentum and the two stress moments
+// (C1, C4, C6, C8, C9) are fixed; the moments e, eps, q_x, q_y (rows 2, 3, 5,
+// 7 of T) are free and take one Newton-Raphson step on the divergence
+// H(p) = sum p ln(p/W), starting from the moments of the polynomial
+// equilibrium.  The step is taken here in population space f = rho p with the
+// free columns of T^-1 scaled to integers:
+//   a_e  = (-4,-1,-1,-1,-1, 2, 2, 2, 2)      a_eps = ( 4,-2,-2,-2,-2, 1, 1, 1, 1)
+//   a_qx = ( 0,-2, 0, 2, 0, 1,-1,-1, 1)      a_qy  = ( 0, 0,-2, 0, 2, 1, 1,-1,-1)
+// Newton's step is affine invariant, so with A = [a_e a_eps a_qx a_qy]:
+//   g = A^T ln(f0/W),  H = A^T diag(1/f0) A,  f_post = f0 - A H^-1 g
+// equals rho times the step in probability space with the paper's scaling
+// (the column scales and rho cancel; the "+1" of the gradient and ln rho
+// drop out because every free column sums to zero).
+//
+// The start point f0 = T^-1 M0 is the polynomial equilibrium plus the stress
+// part of the pre-collision state scaled by (1 - 1/tau):
+//   f0 = feq + (1 - 1/tau) [ (P_xx-yy - rho(ux^2-uy^2)) T^-1_col8 + (P_xy - rho ux uy) T^-1_col9 ]
+// with T^-1_col8 = (0,1,-1,1,-1,0,0,0,0)/4 and T^-1_col9 = (0,0,0,0,0,1,-1,1,-1)/4.
+//
+// Two evaluations of g:
+//   PRODUCT  (double): g is the log of a product of population ratios that
+//            are each close to one, four logarithms per node;
+//   DEVIATION (float): f0_a = W_a rho (1 + e_a) with e_a built from small
+//            terms only, and ln(f0_a/W_a) = ln rho + log1p(e_a); nine log1p
+//            per node, no cancellation in single precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Rounded weights of the D2Q9 set (Table I) in compute precision.
+template <class C>
+struct W9 {
+    static constexpr C rest = C(4.0 / 9.0);
+    static constexpr C axis = C(1.0 / 9.0);
+    static constexpr C diag = C(1.0 / 36.0);
+};
+
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    return r;
+}
+
+__device__ __forceinline__ float rcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
+__device__ __forceinline__ double ln(double x) { return log(x); }
+__device__ __forceinline__ float ln1p(float x) { return log1pf(x); }
+
+template <class C>
+__device__ __forceinline__ bool positive_finite(C v)
+{
+    // false for v <= 0, NaN and +inf
+    return v > C(0) && v < C(__builtin_huge_valf());
+}
+
+template <class C>
+__device__ __forceinline__ bool nonneg_finite(C v)
+{
+    return v >= C(0) && v < C(__builtin_huge_valf());
+}
+
+// Polynomial equilibrium (Sec. IV.E) of (rho, ux, uy) in direction order.
+template <class C>
+__device__ __forceinline__ void equilibrium(C rho, C ux, C uy, C (&feq)[9])
+{
+    const C b = C(1) - C(1.5) * (ux * ux + uy * uy);
+    const C wr = W9<C>::rest * rho, wa = W9<C>::axis * rho, wd = W9<C>::diag * rho;
+    const C s = ux + uy, d = ux - uy;
+    const C xx = C(4.5) * ux * ux + b, yy = C(4.5) * uy * uy + b;
+    const C ss = C(4.5) * s * s + b, dd = C(4.5) * d * d + b;
+    feq[0] = wr * b;
+    feq[1] = wa * (xx + C(3) * ux);
+    feq[2] = wa * (yy + C(3) * uy);
+    feq[3] = wa * (xx - C(3) * ux);
+    feq[4] = wa * (yy - C(3) * uy);
+    feq[5] = wd * (ss + C(3) * s);
+    feq[6] = wd * (dd - C(3) * d);
+    feq[7] = wd * (ss - C(3) * s);
+    feq[8] = wd * (dd + C(3) * d);
+}
+
+// LDL^T solve of the symmetric positive definite n x n system H x = g
+// (n = 2 or 4) held in registers.  Unknown order: e, eps, qx, qy.
+template <class C>
+struct Sym4 {
+    C ee, ep, pp, ex, px, xx, ey, py, xy, yy;
+};
+
+template <class C>
+__device__ __forceinline__ void ldlt_solve4(const Sym4<C> &h, C (&g)[4])
+{
+    const C d0 = h.ee, i0 = rcp(d0);
+    const C l10 = h.ep * i0, l20 = h.ex * i0, l30 = h.ey * i0;
+    const C d1 = h.pp - l10 * h.ep, i1 = rcp(d1);
+    const C t21 = h.px - l20 * h.ep, t31 = h.py - l30 * h.ep;
+    const C l21 = t21 * i1, l31 = t31 * i1;
+    const C d2 = h.xx - l20 * h.ex - l21 * t21, i2 = rcp(d2);
+    const C t32 = h.xy - l30 * h.ex - l31 * t21;
+    const C l32 = t32 * i2;
+    const C d3 = h.yy - l30 * h.ey - l31 * t31 - l32 * t32, i3 = rcp(d3);
+    // forward (unit lower), diagonal, backward
+    const C z0 = g[0];
+    const C z1 = g[1] - l10 * z0;
+    const C z2 = g[2] - l20 * z0 - l21 * z1;
+    const C z3 = g[3] - l30 * z0 - l31 * z1 - l32 * z2;
+    const C x3 = z3 * i3;
+    const C x2 = z2 * i2 - l32 * x3;
+    const C x1 = z1 * i1 - l21 * x2 - l31 * x3;
+    const C x0 = z0 * i0 - l10 * x1 - l20 * x2 - l30 * x3;
+    g[0] = x0;
+    g[1] = x1;
+    g[2] = x2;
+    g[3] = x3;
+}
+
+// SRT / BGK (Sec. II.B.1): f += (feq - f) / tau.
+template <class C>
+__device__ __forceinline__ void collide_srt(C (&f)[9], C omega)
+{
+    const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const C irho = rcp(rho);
+    C feq[9];
+    equilibrium(rho, jx * irho, jy * irho, feq);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) f[a] = f[a] + omega * (feq[a] - f[a]);
+}
+
+// MinxEnt collision with a single Newton step.  MX2 selects MinxEnt2 (only
+// e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).  DEVLOG selects the
+// deviation evaluation of the gradient (see the file comment).  Returns true
+// if the node was guarded: its start point had a population <= 0 or not
+// finite, in which case f holds the start point itself (no Newton step).
+template <class C, bool DEVLOG, bool MX2>
+__device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
+{
+    // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C).
+    const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const C pxxyy = (f[1] + f[3]) - (f[2] + f[4]);  // sum f (vx^2 - vy^2)
+    const C pxy = (f[5] + f[7]) - (f[6] + f[8]);    // sum f vx vy
+    const C irho = rcp(rho);
+    const C ux = jx * irho, uy = jy * irho;
+    // Relaxed stress constraints C8, C9 as deviations from equilibrium.
+    const C k = C(1) - omega;
+    const C q8 = C(0.25) * k * (pxxyy - (jx * ux - jy * uy));
+    const C q9 = C(0.25) * k * (pxy - jx * uy);
+    // MinxEnt2: C5 and C7 relaxed with 1/tau2 (T^-1 columns = rows / 12).
+    C q5 = C(0), q7 = C(0);
+    if (MX2) {
+        const C k2 = C(1) - omega2;
+        const C m5 = C(2) * (f[3] - f[1]) + (f[5] - f[6]) + (f[8] - f[7]);
+        const C m7 = C(2) * (f[4] - f[2]) + (f[5] + f[6]) - (f[7] + f[8]);
+        q5 = k2 * (m5 + jx) * C(1.0 / 12.0);
+        q7 = k2 * (m7 + jy) * C(1.0 / 12.0);
+    }
+    // Start point: equilibrium part e_a (deviation from W_a rho) and the
+    // non-equilibrium corrections c_a.
+    const C b = -C(1.5) * (ux * ux + uy * uy);
+    const C s = ux + uy, d = ux - uy;
+    C e[9], c[9];
+    e[0] = b;
+    e[1] = C(4.5) * ux * ux + b + C(3) * ux;
+    e[2] = C(4.5) * uy * uy + b + C(3) * uy;
+    e[3] = C(4.5) * ux * ux + b - C(3) * ux;
+    e[4] = C(4.5) * uy * uy + b - C(3) * uy;
+    e[5] = C(4.5) * s * s + b + C(3) * s;
+    e[6] = C(4.5) * d * d + b - C(3) * d;
+    e[7] = C(4.5) * s * s + b - C(3) * s;
+    e[8] = C(4.5) * d * d + b + C(3) * d;
+    c[0] = C(0);
+    c[1] = q8 - C(2) * q5;
+    c[2] = -q8 - C(2) * q7;
+    c[3] = q8 + C(2) * q5;
+    c[4] = -q8 + C(2) * q7;
+    c[5] = q9 + q5 + q7;
+    c[6] = -q9 - q5 + q7;
+    c[7] = q9 - q5 - q7;
+    c[8] = -q9 + q5 - q7;
+    const C wr = W9<C>::rest * rho, wa = W9<C>::axis * rho, wd = W9<C>::diag * rho;
+    C f0[9];
+    f0[0] = wr + wr * e[0];
+#pragma unroll
+    for (int a = 1; a < 5; ++a) f0[a] = (wa + wa * e[a]) + c[a];
+#pragma unroll
+    for (int a = 5; a < 9; ++a) f0[a] = (wd + wd * e[a]) + c[a];
+
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) ok = ok && positive_finite(f0[a]);
+    if (!ok) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = f0[a];
+        return true;
+    }
+    C r[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
+
+    // Gradient g = A^T ln(f0 / W).
+    C g[4];
+    if (DEVLOG) {
+        // e_a + c_a / (W_a rho): the full relative deviation of f0_a.
+        C L[9];
+        const C ia = irho * C(9), id = irho * C(36);
+        L[0] = ln1p(e[0]);
+#pragma unroll
+        for (int a = 1; a < 5; ++a) L[a] = ln1p(e[a] + c[a] * ia);
+#pragma unroll
+        for (int a = 5; a < 9; ++a) L[a] = ln1p(e[a] + c[a] * id);
+        const C La = (L[1] + L[2]) + (L[3] + L[4]);
+        const C Ld = (L[5] + L[6]) + (L[7] + L[8]);
+        g[0] = C(2) * Ld - La - C(4) * L[0];
+        g[1] = Ld - C(2) * La + C(4) * L[0];
+        g[2] = C(2) * (L[3] - L[1]) + (L[5] + L[8]) - (L[6] + L[7]);
+        g[3] = C(2) * (L[4] - L[2]) + (L[5] + L[6]) - (L[7] + L[8]);
+    } else {
+        // Products of ratios, each near one at equilibrium:
+        //  g_e   = ln( 2^24 (f5 f6 f7 f8)^2 r0^4 r1 r2 r3 r4 )
+        //  g_eps = ln( f0^4 f5 f6 f7 f8 (r1 r2 r3 r4)^2 )
+        //  g_qx  = ln( (f3 r1)^2 f5 f8 r6 r7 ),  g_qy = ln( (f4 r2)^2 f5 f6 r7 r8 )
+        // (2^24 = prod W_a^(-a_e,a), the only non-zero weight term).
+        const C X = ((f0[5] * r[1]) * (f0[6] * r[2])) * ((f0[7] * r[3]) * (f0[8] * r[4]));
+        const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
+        const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));
+        const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
+        g[0] = ln((Pe * X) * C(16777216.0));
+        g[1] = ln(Pp * X);
+        g[2] = ln((t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7])));
+        g[3] = ln((t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8])));
+    }
+
+    // Hessian H = A^T diag(r) A.
+    const C Sa = (r[1] + r[2]) + (r[3] + r[4]);
+    const C Sd = (r[5] + r[6]) + (r[7] + r[8]);
+    Sym4<C> h;
+    h.ee = C(16) * r[0] + Sa + C(4) * Sd;
+    h.ep = C(2) * (Sa + Sd) - C(16) * r[0];
+    h.pp = C(16) * r[0] + C(4) * Sa + Sd;
+
+    C de, dp, dx = C(0), dy = C(0);
+    if (MX2) {
+        // Two free moments: closed-form 2 x 2 solve.
+        const C det = h.ee * h.pp - h.ep * h.ep;
+        const C idet = rcp(det);
+        de = (h.pp * g[0] - h.ep * g[1]) * idet;
+        dp = (h.ee * g[1] - h.ep * g[0]) * idet;
+    } else {
+        const C Dx = (r[5] + r[8]) - (r[6] + r[7]);
+        const C Dy = (r[5] + r[6]) - (r[7] + r[8]);
+        h.ex = C(2) * ((r[1] - r[3]) + Dx);
+        h.px = C(4) * (r[1] - r[3]) + Dx;
+        h.ey = C(2) * ((r[2] - r[4]) + Dy);
+        h.py = C(4) * (r[2] - r[4]) + Dy;
+        h.xx = C(4) * (r[1] + r[3]) + Sd;
+        h.yy = C(4) * (r[2] + r[4]) + Sd;
+        h.xy = (r[5] + r[7]) - (r[6] + r[8]);
+        ldlt_solve4(h, g);
+        de = g[0];
+        dp = g[1];
+        dx = g[2];
+        dy = g[3];
+    }
+
+    // f_post = f0 - A delta.
+    const C axis = de + C(2) * dp;
+    const C dgn = C(2) * de + dp;
+    f[0] = f0[0] + C(4) * (de - dp);
+    f[1] = f0[1] + (axis + C(2) * dx);
+    f[2] = f0[2] + (axis + C(2) * dy);
+    f[3] = f0[3] + (axis - C(2) * dx);
+    f[4] = f0[4] + (axis - C(2) * dy);
+    f[5] = f0[5] - (dgn + (dx + dy));
+    f[6] = f0[6] - (dgn - (dx - dy));
+    f[7] = f0[7] - (dgn - (dx + dy));
+    f[8] = f0[8] - (dgn + (dx - dy));
+    return false;
+}
+
+}  // namespace lbm

@@ -1,0 +1,745 @@
+// kernels.hip -- fused stream-and-collide kernels of MinxEnt-LBM for gfx950.
+//
+// One thread owns one node per row it visits.  Each time step it pulls the
+// nine (or three) populations that stream into its node from the previous
+// post-collision state (Sec. II.A: f_a(x + v_a, t+1) = post-collision f_a(x, t),
+// read here as f_a(x) <- f*_a(x - v_a)), applies the node's role -- the
+// collision rule on fluid nodes, full-way bounce-back on walls, the
+// equilibrium of the lid's density and velocity on the lid (Sec. IV.E) -- and
+// writes its nine post-collision populations to the other buffer.
+//
+// Layout: structure of arrays, one plane of nx*ny values per direction,
+// x fastest, so every plane read is a unit-stride row shifted by at most one
+// element and every write is aligned and unit-stride.  Populations are read
+// and written exactly once per step; the kernels are bound by HBM bandwidth
+// and by FP64 VALU issue (logarithms and reciprocals of the Newton step).
+//
+// Slots of boundary nodes whose upstream node lies outside the lattice read a
+// clamped (in-bounds) location; their values are bounced outward and never
+// reach a fluid node.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "collide.hpp"
+#include "kernels.hpp"
+
+namespace lbm {
+
+// --------------------------------------------------------------------------
+// Storage forms
+// --------------------------------------------------------------------------
+
+template <int ST> struct Form;
+template <> struct Form<ST_F64> { using T = double; using C = double; static constexpr bool DEVLOG = false; };
+template <> struct Form<ST_F32N64> { using T = float; using C = double; static constexpr bool DEVLOG = false; };
+template <> struct Form<ST_F32> { using T = float; using C = float; static constexpr bool DEVLOG = true; };
+template <> struct Form<ST_F16DEV> { using T = _Float16; using C = float; static constexpr bool DEVLOG = true; };
+
+template <int ST>
+__device__ __forceinline__ typename Form<ST>::C load(const typename Form<ST>::T *p, typename Form<ST>::C ref,
+                                                     float iscale)
+{
+    using C = typename Form<ST>::C;
+    if constexpr (ST == ST_F16DEV) return ref + C(*p) * iscale;
+    else return C(*p);
+}
+
+template <int ST>
+__device__ __forceinline__ void store(typename Form<ST>::T *p, typename Form<ST>::C v, typename Form<ST>::C ref,
+                                      float scale)
+{
+    using T = typename Form<ST>::T;
+    if constexpr (ST == ST_F16DEV) *p = T((v - ref) * scale);
+    else *p = T(v);
+}
+
+template <class C>
+__device__ __forceinline__ void ref9(C rho0, C (&r)[9])
+{
+    r[0] = W9<C>::rest * rho0;
+#pragma unroll
+    for (int a = 1; a < 5; ++a) r[a] = W9<C>::axis * rho0;
+#pragma unroll
+    for (int a = 5; a < 9; ++a) r[a] = W9<C>::diag * rho0;
+}
+
+// D2Q9 direction table (pull offsets are the negated velocities).
+__device__ __forceinline__ int cx9(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : (a == 3 || a == 6 || a == 7) ? -1 : 0; }
+__device__ __forceinline__ int cy9(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : (a == 4 || a == 7 || a == 8) ? -1 : 0; }
+
+// Neighbour rows and columns of (x, y): wrapped on periodic axes, clamped
+// otherwise.
+struct Nb {
+    int xm, xp, ym, yp;
+};
+
+__device__ __forceinline__ Nb neighbours(int x, int y, int nx, int ny, int bc)
+{
+    const bool xw = bc == BC_PERIODIC;
+    const bool yw = bc == BC_PERIODIC || bc == BC_TUBE;
+    Nb n;
+    n.xm = x > 0 ? x - 1 : (xw ? nx - 1 : 0);
+    n.xp = x < nx - 1 ? x + 1 : (xw ? 0 : nx - 1);
+    n.ym = y > 0 ? y - 1 : (yw ? ny - 1 : 0);
+    n.yp = y < ny - 1 ? y + 1 : (yw ? 0 : ny - 1);
+    return n;
+}
+
+enum Role { R_FLUID = 0, R_WALL = 1, R_LID = 2 };
+
+__device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
+{
+    switch (bc) {
+    case BC_CAVITY:
+        if (y == ny - 1) return R_LID;
+        return (x == 0 || x == nx - 1 || y == 0) ? R_WALL : R_FLUID;
+    case BC_BOX:
+        return (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) ? R_WALL : R_FLUID;
+    case BC_TUBE:
+        return (x == 0 || x == nx - 1) ? R_WALL : R_FLUID;
+    default:
+        return R_FLUID;
+    }
+}
+
+// Pull the nine populations that stream into node (x, y).
+template <int ST>
+__device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
+                                      const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
+                                      typename Form<ST>::C (&f)[9])
+{
+    const int rc = y * nx, rm = n.ym * nx, rp = n.yp * nx;
+    f[0] = load<ST>(s + rc + x, ref[0], iscale);
+    f[1] = load<ST>(s + P + rc + n.xm, ref[1], iscale);
+    f[2] = load<ST>(s + 2 * P + rm + x, ref[2], iscale);
+    f[3] = load<ST>(s + 3 * P + rc + n.xp, ref[3], iscale);
+    f[4] = load<ST>(s + 4 * P + rp + x, ref[4], iscale);
+    f[5] = load<ST>(s + 5 * P + rm + n.xm, ref[5], iscale);
+    f[6] = load<ST>(s + 6 * P + rm + n.xp, ref[6], iscale);
+    f[7] = load<ST>(s + 7 * P + rp + n.xp, ref[7], iscale);
+    f[8] = load<ST>(s + 8 * P + rp + n.xm, ref[8], iscale);
+}
+
+// Role collision of one D2Q9 node.  Returns bit 0 = unstable, bit 1 = guarded.
+template <int ST, int CO>
+__device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, const Inst &in)
+{
+    using C = typename Form<ST>::C;
+    if (role == R_LID) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = C(in.lid[a]);
+        return 0;
+    }
+    if (role == R_WALL) {
+        C t;
+        t = f[1]; f[1] = f[3]; f[3] = t;
+        t = f[2]; f[2] = f[4]; f[4] = t;
+        t = f[5]; f[5] = f[7]; f[7] = t;
+        t = f[6]; f[6] = f[8]; f[8] = t;
+        return 0;
+    }
+    int flags = 0;
+    if constexpr (CO == CO_SRT) {
+        collide_srt<C>(f, C(in.omega));
+    } else {
+        const bool g = collide_minxent<C, Form<ST>::DEVLOG, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2));
+        flags |= g ? 2 : 0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) ok = ok && nonneg_finite(f[a]);
+    return flags | (ok ? 0 : 1);
+}
+
+// Wave-level status update: one atomic per wave and kind.
+__device__ __forceinline__ void report(DevStatus *st, bool unstable, int guarded_in_wave, int64_t step,
+                                       const int64_t *step_base)
+{
+    const unsigned long long m = __ballot(unstable);
+    if ((m != 0ull || guarded_in_wave != 0) && __lane_id() == 0) {
+        if (m != 0ull) {
+            const int64_t s = step + (step_base ? *step_base : 0);
+            atomicOr(&st->flags, 1u);
+            atomicMin((unsigned long long *)&st->first_step, (unsigned long long)s);
+        }
+        if (guarded_in_wave != 0) {
+            atomicOr(&st->flags, 2u);
+            atomicAdd((unsigned long long *)&st->guarded, (unsigned long long)guarded_in_wave);
+        }
+    }
+}
+
+// Map block b of a grid of nb blocks so that the blocks the hardware sends to
+// one XCD (b, b+8, b+16, ...) cover a contiguous range of tiles.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, k = b & 7;
+    return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+// --------------------------------------------------------------------------
+// D2Q9, one lattice.  Block = BX x BY threads (BX a multiple of 64, so a wave
+// never spans two rows); it covers BX columns and BY*RPT rows.
+// --------------------------------------------------------------------------
+
+template <int ST, int CO, int BX, int BY, int RPT>
+__global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__restrict__ src,
+                                                 typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    const Inst &in = a.one;
+    const int nx = in.nx, ny = in.ny;
+    const int64_t P = in.plane;
+    int b = blockIdx.x;
+    if (a.xcd_swizzle) b = xcd_remap(b, gridDim.x);
+    const int tx = b % a.tiles_x, ty = b / a.tiles_x;
+    const int x = tx * BX + (int)threadIdx.x;
+    const bool xin = x < nx;
+    const int xs = xin ? x : nx - 1;
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+    bool bad = false;
+    int guarded = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = (ty * RPT + k) * BY + (int)threadIdx.y;
+        if (y >= ny) break;  // wave-uniform: a wave lies in one row
+        const Nb n = neighbours(xs, y, nx, ny, a.bc);
+        C f[9];
+        pull9<ST>(src, P, xs, y, nx, n, ref, a.fp16_iscale, f);
+        const int role = role9(xs, y, nx, ny, a.bc);
+        const int fl = node9<ST, CO>(f, role, in);
+        bad = bad || (xin && (fl & 1));
+        guarded += __popcll(__ballot(xin && (fl & 2)));
+        if (xin) {
+            typename Form<ST>::T *d = dst + y * nx + x;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) store<ST>(d + q * P, f[q], ref[q], a.fp16_scale);
+        }
+    }
+    report(a.status, bad, guarded, a.step, a.step_base);
+}
+
+// --------------------------------------------------------------------------
+// D2Q9, batch of lattices.  A tile is BLK consecutive nodes (row-major) of
+// one instance; tile tables give its instance and first node.
+// --------------------------------------------------------------------------
+
+template <int ST, int CO, int BLK>
+__global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *__restrict__ src,
+                                                    typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    int t = blockIdx.x;
+    if (a.xcd_swizzle) t = xcd_remap(t, gridDim.x);
+    const int i = a.tile_inst[t];
+    const Inst &in = a.inst[i];
+    const int nx = in.nx, ny = in.ny;
+    const int64_t P = in.plane;
+    const int nodes = nx * ny;
+    int node = a.tile_first[t] + (int)threadIdx.x;
+    const bool valid = node < nodes;
+    if (!valid) node = nodes - 1;
+    // node -> (x, y): float estimate, exact after one correction (node < 2^24).
+    int y = (int)((float)node * __builtin_amdgcn_rcpf((float)nx));
+    int x = node - y * nx;
+    if (x < 0) { --y; x += nx; }
+    if (x >= nx) { ++y; x -= nx; }
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+    const Nb n = neighbours(x, y, nx, ny, a.bc);
+    const typename Form<ST>::T *s = src + in.offset;
+    C f[9];
+    pull9<ST>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
+    const int role = role9(x, y, nx, ny, a.bc);
+    const int fl = node9<ST, CO>(f, role, in);
+    if (valid) {
+        typename Form<ST>::T *d = dst + in.offset + node;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) store<ST>(d + q * P, f[q], ref[q], a.fp16_scale);
+    }
+    const int guarded = __popcll(__ballot(valid && (fl & 2)));
+    report(a.status + i, valid && (fl & 1), guarded, a.step, a.step_base);
+}
+
+// --------------------------------------------------------------------------
+// D1Q3 (rest, +1, -1): SRT, the exact form of the method on this lattice.
+// --------------------------------------------------------------------------
+
+template <class C>
+__device__ __forceinline__ int node3(C &f0, C &fp, C &fm, int role, C omega)
+{
+    if (role == R_WALL) {
+        const C t = fp;
+        fp = fm;
+        fm = t;
+        return 0;
+    }
+    const C rho = (f0 + fp) + fm;
+    const C u = (fp - fm) * rcp(rho);
+    const C uu = u * u;
+    const C e0 = C(2.0 / 3.0) * rho * (C(1) - C(1.5) * uu);
+    const C es = C(1.0 / 6.0) * rho * (C(1) + C(3) * uu);
+    const C eu = C(1.0 / 6.0) * rho * (C(3) * u);
+    f0 = f0 + omega * (e0 - f0);
+    fp = fp + omega * ((es + eu) - fp);
+    fm = fm + omega * ((es - eu) - fm);
+    return (nonneg_finite(f0) && nonneg_finite(fp) && nonneg_finite(fm)) ? 0 : 1;
+}
+
+template <int ST>
+__device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict__ s,
+                                          typename Form<ST>::T *__restrict__ d, int64_t P, int x, int nx,
+                                          int bc, typename Form<ST>::C omega, typename Form<ST>::C rho0,
+                                          const StepArgs &a, bool valid)
+{
+    using C = typename Form<ST>::C;
+    const bool wrap = bc == BC_PERIODIC;
+    const int xm = x > 0 ? x - 1 : (wrap ? nx - 1 : 0);
+    const int xp = x < nx - 1 ? x + 1 : (wrap ? 0 : nx - 1);
+    const C r0 = C(2.0 / 3.0) * rho0, r1 = C(1.0 / 6.0) * rho0;
+    C f0 = load<ST>(s + x, r0, a.fp16_iscale);
+    C fp = load<ST>(s + P + xm, r1, a.fp16_iscale);
+    C fm = load<ST>(s + 2 * P + xp, r1, a.fp16_iscale);
+    const int role = (bc != BC_PERIODIC && (x == 0 || x == nx - 1)) ? R_WALL : R_FLUID;
+    const int fl = node3<C>(f0, fp, fm, role, omega);
+    if (valid) {
+        store<ST>(d + x, f0, r0, a.fp16_scale);
+        store<ST>(d + P + x, fp, r1, a.fp16_scale);
+        store<ST>(d + 2 * P + x, fm, r1, a.fp16_scale);
+    }
+    return fl;
+}
+
+template <int ST, int BX, int NPT>
+__global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restrict__ src,
+                                             typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    const Inst &in = a.one;
+    const int nx = in.nx;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int x = (blockIdx.x * NPT + k) * BX + (int)threadIdx.x;
+        const bool valid = x < nx;
+        const int fl = step3_node<ST>(src, dst, in.plane, valid ? x : nx - 1, nx, a.bc, C(in.omega),
+                                      C(in.rho0), a, valid);
+        bad = bad || (valid && fl);
+    }
+    report(a.status, bad, 0, a.step, a.step_base);
+}
+
+template <int ST, int BLK>
+__global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *__restrict__ src,
+                                                    typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    int t = blockIdx.x;
+    if (a.xcd_swizzle) t = xcd_remap(t, gridDim.x);
+    const int i = a.tile_inst[t];
+    const Inst &in = a.inst[i];
+    const int nx = in.nx;
+    const int x = a.tile_first[t] + (int)threadIdx.x;
+    const bool valid = x < nx;
+    const int fl = step3_node<ST>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
+                                  C(in.omega), C(in.rho0), a, valid);
+    report(a.status + i, valid && fl, 0, a.step, a.step_base);
+}
+
+// --------------------------------------------------------------------------
+// State set-up and read-back (off the hot loop; FP64 in and out).
+// --------------------------------------------------------------------------
+
+// Storage node (x, y) receives, for each direction a, the value that node
+// (x, y) + v_a must pull at the next step: the equilibrium of that node's
+// fields (or the given populations).  Destinations outside the lattice take
+// the node's own value.
+template <int ST, int B>
+__global__ void k_init(Inst in, int bc, const double *__restrict__ rho, const double *__restrict__ ux,
+                       const double *__restrict__ uy, const double *__restrict__ fin, typename Form<ST>::T *buf,
+                       float scale)
+{
+    using C = typename Form<ST>::C;
+    const int nx = in.nx, ny = in.ny;
+    const int n = nx * ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = i % nx, y = i / nx;
+    const bool xw = bc == BC_PERIODIC;
+    const bool yw = (bc == BC_PERIODIC || bc == BC_TUBE) && B == 9;
+    typename Form<ST>::T *d = buf + in.offset;
+    for (int a = 0; a < B; ++a) {
+        const int vx = (B == 9) ? cx9(a) : (a == 1 ? 1 : (a == 2 ? -1 : 0));
+        const int vy = (B == 9) ? cy9(a) : 0;
+        int tx = x + vx, ty = y + vy;
+        if (tx < 0 || tx >= nx) tx = xw ? (tx + nx) % nx : x;
+        if (ty < 0 || ty >= ny) ty = yw ? (ty + ny) % ny : y;
+        if ((tx == x && vx != 0 && !xw) || (ty == y && vy != 0 && !yw)) { tx = x; ty = y; }
+        const int j = ty * nx + tx;
+        double v;
+        if (fin) {
+            v = fin[(int64_t)a * n + j];
+        } else if (B == 9 && bc == BC_CAVITY && ty == ny - 1) {
+            v = in.lid[a];
+        } else {
+            const double r = rho[j], u = ux[j], w = (B == 9) ? uy[j] : 0.0;
+            const double cu = vx * u + vy * w;
+            const double wa = (B == 9) ? ((a == 0) ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0))
+                                       : (a == 0 ? 2.0 / 3.0 : 1.0 / 6.0);
+            v = wa * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (u * u + w * w));
+        }
+        C ref;
+        if (B == 9) {
+            ref = (a == 0 ? W9<C>::rest : (a < 5 ? W9<C>::axis : W9<C>::diag)) * C(in.rho0);
+        } else {
+            ref = (a == 0 ? C(2.0 / 3.0) : C(1.0 / 6.0)) * C(in.rho0);
+        }
+        store<ST>(d + (int64_t)a * in.plane + i, C(v), ref, scale);
+    }
+}
+
+template <int ST, int B>
+__global__ void k_gather(Inst in, int bc, const typename Form<ST>::T *__restrict__ buf, double *rho, double *ux,
+                         double *uy, double *fout, float iscale)
+{
+    using C = typename Form<ST>::C;
+    const int nx = in.nx, ny = in.ny;
+    const int n = nx * ny;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = i % nx, y = i / nx;
+    const typename Form<ST>::T *s = buf + in.offset;
+    double f[9];
+    if (B == 9) {
+        C ref[9];
+        ref9<C>(C(in.rho0), ref);
+        C g[9];
+        pull9<ST>(s, in.plane, x, y, nx, neighbours(x, y, nx, ny, bc), ref, iscale, g);
+        for (int a = 0; a < 9; ++a) f[a] = double(g[a]);
+    } else {
+        const bool wrap = bc == BC_PERIODIC;
+        const int xm = x > 0 ? x - 1 : (wrap ? nx - 1 : 0);
+        const int xp = x < nx - 1 ? x + 1 : (wrap ? 0 : nx - 1);
+        const C r0 = C(2.0 / 3.0) * C(in.rho0), r1 = C(1.0 / 6.0) * C(in.rho0);
+        f[0] = double(load<ST>(s + x, r0, iscale));
+        f[1] = double(load<ST>(s + in.plane + xm, r1, iscale));
+        f[2] = double(load<ST>(s + 2 * in.plane + xp, r1, iscale));
+    }
+    if (fout) {
+        for (int a = 0; a < B; ++a) fout[(int64_t)a * n + i] = f[a];
+        return;
+    }
+    double r, jx, jy;
+    if (B == 9) {
+        r = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+        jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+        jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+    } else {
+        r = f[0] + f[1] + f[2];
+        jx = f[1] - f[2];
+        jy = 0.0;
+    }
+    if (rho) rho[i] = r;
+    if (ux) ux[i] = jx / r;
+    if (uy) uy[i] = jy / r;
+}
+
+__global__ void k_copy(uint4 *__restrict__ d, const uint4 *__restrict__ s, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) d[i] = s[i];
+}
+
+__global__ void k_step_base(int64_t *b, int64_t v, int add)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *b = add ? *b + v : v;
+}
+
+__global__ void k_clear_status(DevStatus *st, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        st[i].flags = 0;
+        st[i].pad = 0;
+        st[i].first_step = INT64_MAX;
+        st[i].guarded = 0;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Launchers
+// --------------------------------------------------------------------------
+
+namespace {
+
+struct Shape {
+    int bx, by, rpt, swz;
+    const char *name;
+};
+
+// Launch shapes of the single-lattice D2Q9 kernel.  Every shape computes the
+// same per-node arithmetic, so results are bitwise identical.
+constexpr Shape kShapes[] = {
+    {256, 1, 1, 0, "256x1 rows=1 linear"},
+    {256, 1, 1, 1, "256x1 rows=1 xcd"},
+    {64, 4, 1, 1, "64x4 rows=1 xcd"},
+    {128, 2, 1, 1, "128x2 rows=1 xcd"},
+    {256, 1, 2, 1, "256x1 rows=2 xcd"},
+    {64, 4, 2, 1, "64x4 rows=2 xcd"},
+    {64, 2, 1, 1, "64x2 rows=1 xcd"},
+    {128, 1, 1, 1, "128x1 rows=1 xcd"},
+};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kNumShapesOther = 3;  // MinxEnt2 / SRT instantiate the first three
+
+template <int ST, int CO, int BX, int BY, int RPT>
+hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int tiles_x = (a.one.nx + BX - 1) / BX;
+    const int tiles_y = (a.one.ny + BY * RPT - 1) / (BY * RPT);
+    a.tiles_x = tiles_x;
+    a.xcd_swizzle = swz;
+    hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT>), dim3(tiles_x * tiles_y), dim3(BX, BY), 0, s,
+                       (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST, int CO>
+hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    const int swz = kShapes[v].swz;
+    switch (v) {
+    case 0: return go9<ST, CO, 256, 1, 1>(src, dst, a, swz, s);
+    case 1: return go9<ST, CO, 256, 1, 1>(src, dst, a, swz, s);
+    case 2: return go9<ST, CO, 64, 4, 1>(src, dst, a, swz, s);
+    default: break;
+    }
+    if constexpr (CO == CO_MINXENT4) {
+        switch (v) {
+        case 3: return go9<ST, CO, 128, 2, 1>(src, dst, a, swz, s);
+        case 4: return go9<ST, CO, 256, 1, 2>(src, dst, a, swz, s);
+        case 5: return go9<ST, CO, 64, 4, 2>(src, dst, a, swz, s);
+        case 6: return go9<ST, CO, 64, 2, 1>(src, dst, a, swz, s);
+        case 7: return go9<ST, CO, 128, 1, 1>(src, dst, a, swz, s);
+        default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int ST>
+hipError_t dispatch9c(int coll, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    switch (coll) {
+    case CO_MINXENT4: return dispatch9<ST, CO_MINXENT4>(v, src, dst, a, s);
+    case CO_MINXENT2: return dispatch9<ST, CO_MINXENT2>(v, src, dst, a, s);
+    case CO_SRT: return dispatch9<ST, CO_SRT>(v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+constexpr int kBatchBlocks[] = {256, 128};
+
+template <int ST, int CO>
+hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    if (v == 0)
+        hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a);
+    else
+        hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 128>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t dispatch9bc(int coll, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    switch (coll) {
+    case CO_MINXENT4: return dispatch9b<ST, CO_MINXENT4>(v, src, dst, a, s);
+    case CO_MINXENT2: return dispatch9b<ST, CO_MINXENT2>(v, src, dst, a, s);
+    case CO_SRT: return dispatch9b<ST, CO_SRT>(v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+struct Shape3 {
+    int bx, npt;
+    const char *name;
+};
+constexpr Shape3 kShapes3[] = {
+    {256, 1, "256 nodes=1"},
+    {256, 4, "256 nodes=4"},
+    {512, 2, "512 nodes=2"},
+    {128, 4, "128 nodes=4"},
+};
+constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
+
+template <int ST, int BX, int NPT>
+hipError_t go3(const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int blocks = (a.one.nx + BX * NPT - 1) / (BX * NPT);
+    hipLaunchKernelGGL((k_d1q3<ST, BX, NPT>), dim3(blocks), dim3(BX), 0, s, (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    switch (v) {
+    case 0: return go3<ST, 256, 1>(src, dst, a, s);
+    case 1: return go3<ST, 256, 4>(src, dst, a, s);
+    case 2: return go3<ST, 512, 2>(src, dst, a, s);
+    case 3: return go3<ST, 128, 4>(src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int ST>
+hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    if (v == 0)
+        hipLaunchKernelGGL((k_d1q3_batch<ST, 256>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a);
+    else
+        hipLaunchKernelGGL((k_d1q3_batch<ST, 128>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t init_st(int lattice, const Inst &in, int bc, const double *r, const double *u, const double *w,
+                   const double *f, void *buf, float scale, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int n = in.nx * in.ny;
+    const int blocks = (n + 255) / 256;
+    if (lattice == 9)
+        hipLaunchKernelGGL((k_init<ST, 9>), dim3(blocks), dim3(256), 0, s, in, bc, r, u, w, f, (T *)buf, scale);
+    else
+        hipLaunchKernelGGL((k_init<ST, 3>), dim3(blocks), dim3(256), 0, s, in, bc, r, u, w, f, (T *)buf, scale);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t gather_st(int lattice, const Inst &in, int bc, const void *buf, double *r, double *u, double *w,
+                     double *f, float iscale, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int n = in.nx * in.ny;
+    const int blocks = (n + 255) / 256;
+    if (lattice == 9)
+        hipLaunchKernelGGL((k_gather<ST, 9>), dim3(blocks), dim3(256), 0, s, in, bc, (const T *)buf, r, u, w, f, iscale);
+    else
+        hipLaunchKernelGGL((k_gather<ST, 3>), dim3(blocks), dim3(256), 0, s, in, bc, (const T *)buf, r, u, w, f, iscale);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int d2q9_variant_count(int coll) { return coll == CO_MINXENT4 ? kNumShapes : kNumShapesOther; }
+const char *d2q9_variant_name(int v) { return (v >= 0 && v < kNumShapes) ? kShapes[v].name : "?"; }
+int d1q3_variant_count() { return kNumShapes3; }
+const char *d1q3_variant_name(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].name : "?"; }
+int batch_variant_count() { return 2; }
+
+hipError_t launch_d2q9_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    if (v < 0 || v >= d2q9_variant_count(coll)) return hipErrorInvalidValue;
+    switch (st) {
+    case ST_F64: return dispatch9c<ST_F64>(coll, v, src, dst, a, s);
+    case ST_F32N64: return dispatch9c<ST_F32N64>(coll, v, src, dst, a, s);
+    case ST_F32: return dispatch9c<ST_F32>(coll, v, src, dst, a, s);
+    case ST_F16DEV: return dispatch9c<ST_F16DEV>(coll, v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_d2q9_batch_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a,
+                                  hipStream_t s)
+{
+    if (v < 0 || v >= batch_variant_count()) return hipErrorInvalidValue;
+    switch (st) {
+    case ST_F64: return dispatch9bc<ST_F64>(coll, v, src, dst, a, s);
+    case ST_F32N64: return dispatch9bc<ST_F32N64>(coll, v, src, dst, a, s);
+    case ST_F32: return dispatch9bc<ST_F32>(coll, v, src, dst, a, s);
+    case ST_F16DEV: return dispatch9bc<ST_F16DEV>(coll, v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_d1q3_step(int st, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    switch (st) {
+    case ST_F64: return dispatch3<ST_F64>(v, src, dst, a, s);
+    case ST_F32N64: return dispatch3<ST_F32N64>(v, src, dst, a, s);
+    case ST_F32: return dispatch3<ST_F32>(v, src, dst, a, s);
+    case ST_F16DEV: return dispatch3<ST_F16DEV>(v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_d1q3_batch_step(int st, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    if (v < 0 || v >= batch_variant_count()) return hipErrorInvalidValue;
+    switch (st) {
+    case ST_F64: return dispatch3b<ST_F64>(v, src, dst, a, s);
+    case ST_F32N64: return dispatch3b<ST_F32N64>(v, src, dst, a, s);
+    case ST_F32: return dispatch3b<ST_F32>(v, src, dst, a, s);
+    case ST_F16DEV: return dispatch3b<ST_F16DEV>(v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_init(int lattice, int st, const Inst &in, int bc, const double *r, const double *u,
+                       const double *w, const double *f, void *buf, float scale, hipStream_t s)
+{
+    switch (st) {
+    case ST_F64: return init_st<ST_F64>(lattice, in, bc, r, u, w, f, buf, scale, s);
+    case ST_F32N64: return init_st<ST_F32N64>(lattice, in, bc, r, u, w, f, buf, scale, s);
+    case ST_F32: return init_st<ST_F32>(lattice, in, bc, r, u, w, f, buf, scale, s);
+    case ST_F16DEV: return init_st<ST_F16DEV>(lattice, in, bc, r, u, w, f, buf, scale, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gather(int lattice, int st, const Inst &in, int bc, const void *buf, double *r, double *u,
+                         double *w, double *f, float iscale, hipStream_t s)
+{
+    switch (st) {
+    case ST_F64: return gather_st<ST_F64>(lattice, in, bc, buf, r, u, w, f, iscale, s);
+    case ST_F32N64: return gather_st<ST_F32N64>(lattice, in, bc, buf, r, u, w, f, iscale, s);
+    case ST_F32: return gather_st<ST_F32>(lattice, in, bc, buf, r, u, w, f, iscale, s);
+    case ST_F16DEV: return gather_st<ST_F16DEV>(lattice, in, bc, buf, r, u, w, f, iscale, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_step_base(int64_t *b, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_base, dim3(1), dim3(64), 0, s, b, n, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step_base(int64_t *b, int64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_base, dim3(1), dim3(64), 0, s, b, v, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_status(DevStatus *st, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_status, dim3((n + 255) / 256), dim3(256), 0, s, st, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,85 @@
+// kernels.hpp -- launch interface between the host runtime and the HIP
+// kernels of the fused stream-and-collide step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum Storage { ST_F64 = 0, ST_F32N64 = 1, ST_F32 = 2, ST_F16DEV = 3 };
+enum Coll { CO_MINXENT4 = 0, CO_MINXENT2 = 1, CO_SRT = 2 };
+enum Bc { BC_PERIODIC = 0, BC_TUBE = 1, BC_CAVITY = 2, BC_BOX = 3 };
+
+// Status record of one instance (device memory).
+struct DevStatus {
+    uint32_t flags;
+    int32_t pad;
+    int64_t first_step;  // INT64_MAX until the first instability
+    int64_t guarded;
+};
+
+// One lattice instance as the kernels see it.  Populations of instance i
+// live in b planes of `plane` elements starting at element `offset` of each
+// of the two buffers; node (x, y) is element y*nx + x of a plane.
+struct Inst {
+    int32_t nx, ny;
+    int64_t offset;
+    int64_t plane;
+    double omega;    // 1/tau
+    double omega2;   // 1/tau2
+    double u_lid;
+    double rho0;
+    double lid[9];   // equilibrium of (rho0, (u_lid, 0))
+};
+
+// Everything a step launch needs besides the buffers.
+struct StepArgs {
+    const Inst *inst;       // device table (batched) -- or nullptr
+    Inst one;               // the single instance (non-batched launches)
+    DevStatus *status;      // one record per instance
+    const int64_t *step_base;  // if not null, added to `step` on the error path
+    const int32_t *tile_inst;  // batched: instance of each tile
+    const int32_t *tile_first; // batched: first node (D1Q3) or first row (D2Q9) of each tile
+    int64_t step;
+    int32_t bc;
+    int32_t ntiles;
+    int32_t tiles_x;        // single D2Q9: tiles along x
+    int32_t xcd_swizzle;
+    float fp16_scale;       // FP16DEV: 2^k
+    float fp16_iscale;      // 2^-k
+};
+
+// Host-side launchers (return hipError_t of the launch).
+int d2q9_variant_count(int coll);
+const char *d2q9_variant_name(int variant);
+hipError_t launch_d2q9_step(int storage, int coll, int variant, const void *src, void *dst,
+                            const StepArgs &a, hipStream_t s);
+hipError_t launch_d2q9_batch_step(int storage, int coll, int variant, const void *src, void *dst,
+                                  const StepArgs &a, hipStream_t s);
+int d1q3_variant_count();
+const char *d1q3_variant_name(int variant);
+hipError_t launch_d1q3_step(int storage, int variant, const void *src, void *dst, const StepArgs &a,
+                            hipStream_t s);
+hipError_t launch_d1q3_batch_step(int storage, int variant, const void *src, void *dst,
+                                  const StepArgs &a, hipStream_t s);
+int batch_variant_count();
+
+// Set the state of one instance: pre-shifted equilibrium of FP64 fields
+// (d_rho, d_ux, d_uy: nx*ny device doubles) or of FP64 populations (d_f:
+// b planes of nx*ny device doubles).
+hipError_t launch_init(int lattice, int storage, const Inst &in, int bc, const double *d_rho,
+                       const double *d_ux, const double *d_uy, const double *d_f, void *buf,
+                       float fp16_scale, hipStream_t s);
+// Gather the pre-collision populations of one instance and write either its
+// moments (d_rho, d_ux, d_uy) or the populations (d_f), as doubles.
+hipError_t launch_gather(int lattice, int storage, const Inst &in, int bc, const void *buf,
+                         double *d_rho, double *d_ux, double *d_uy, double *d_f, float fp16_iscale,
+                         hipStream_t s);
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+hipError_t launch_add_step_base(int64_t *base, int64_t n, hipStream_t s);
+hipError_t launch_set_step_base(int64_t *base, int64_t v, hipStream_t s);
+hipError_t launch_clear_status(DevStatus *st, int n, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/lbm.h declares, its structures match the binding,
+and invalid parameters are rejected before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(lbm_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1801_03863_amd import binding
+    return binding
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for n in ("lbm_init", "lbm_step", "lbm_moments", "lbm_free", "lbm_status", "lbm_init_batch"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = ctypes.CDLL(B.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts(B):
+    assert ctypes.sizeof(B.lbm_params_t) == 64
+    assert ctypes.sizeof(B.lbm_status_t) == 24
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=float("nan")), dict(nx=2), dict(ny=2), dict(lattice="d1q3", ny=4),
+    dict(rho0=0.0), dict(u_lid=float("inf")), dict(fp16_exp=30),
+])
+def test_invalid_parameters_rejected_before_device_work(B, bad):
+    kw = dict(lattice="d2q9", collision="minxent4", bc="cavity", precision="fp64", nx=8, ny=8, tau=0.6)
+    kw.update(bad)
+    p = B.make_params(**kw)
+    n = p.nx * p.ny
+    with pytest.raises(B.LbmError) as ei:
+        B.lbm_init(p, np.ones(n), np.zeros(n), np.zeros(n))
+    assert ei.value.code == B.LBM_EINVAL
+    with pytest.raises(B.LbmError):
+        B.lbm_workspace_bytes(p)
+
+
+def test_workspace_size_formula(B):
+    p = B.make_params("d2q9", "minxent4", "cavity", "fp32", 100, 50, 0.6)
+    plane = (100 * 50 + 63) // 64 * 64
+    assert B.lbm_workspace_bytes(p) == 2 * ((9 * plane * 4 + 255) // 256 * 256)
+    q = B.make_params("d1q3", "srt", "tube", "fp16dev", 1000, 1, 0.6)
+    assert B.lbm_workspace_bytes(q) == 2 * ((3 * 1024 * 2 + 255) // 256 * 256)
+
+
+def test_batch_must_share_forms(B):
+    a = B.make_params("d2q9", "minxent4", "cavity", "fp32", 32, 32, 0.6)
+    b = B.make_params("d2q9", "minxent4", "cavity", "fp64", 40, 40, 0.6)
+    with pytest.raises(B.LbmError):
+        B.lbm_workspace_bytes_batch([a, b])
+    c = B.make_params("d2q9", "minxent4", "cavity", "fp32", 40, 40, 0.7)
+    assert B.lbm_workspace_bytes_batch([a, c]) > 0
+
+
+def test_error_strings(B):
+    assert B._lib.lbm_strerror(B.LBM_EINVAL) == b"invalid argument"

@@ -1,0 +1,264 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs, element by element on fluid nodes.
+
+FP64 tolerance: relative max-abs and relative L2 error of rho, u_x, u_y over
+fluid nodes <= 1e-12 each.
+"""
+import numpy as np
+import pytest
+
+from paper_1801_03863_amd import inputs as I
+from tests.gpu_helpers import B, field_errors, fluid_mask, gpu_run, orc_run, smooth_fields
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def assert_close(g, o, mask, tol, fields=("rho", "ux", "uy"), label=""):
+    errs = field_errors(g, o, mask, fields)
+    print(label, {k: ("%.2e" % v[0], "%.2e" % v[1]) for k, v in errs.items()}, flush=True)
+    for k, (emax, el2) in errs.items():
+        assert emax <= tol and el2 <= tol, (label, k, emax, el2)
+    return errs
+
+
+# --------------------------------------------------------------------------
+# D1Q3
+# --------------------------------------------------------------------------
+
+def test_d1q3_shock_tube_800_fp64():
+    c = I.shock_tube_800()
+    g = gpu_run("d1q3", "srt", "tube", "fp64", 800, 1, c["tau"], c["rho"], c["ux"], steps=c["steps"])
+    o = orc_run("d1q3", "srt", "tube", 800, 1, c["tau"], c["rho"], c["ux"], steps=c["steps"])
+    assert_close(g, o, fluid_mask("d1q3", "tube", 800, 1), TOL64, ("rho", "ux"), "tube800")
+    assert not g["status"]["unstable"] and not o["unstable"]
+
+
+@pytest.mark.parametrize("nx,bc,steps", [(3, "tube", 5), (1000, "periodic", 77), (257, "cavity", 60)])
+def test_d1q3_sizes_and_boundaries(nx, bc, steps):
+    rng = np.random.default_rng(nx)
+    rho = 1 + 0.2 * rng.uniform(-1, 1, nx)
+    ux = 0.05 * rng.uniform(-1, 1, nx)
+    g = gpu_run("d1q3", "srt", bc, "fp64", nx, 1, 0.53, rho, ux, steps=steps)
+    o = orc_run("d1q3", "srt", bc, nx, 1, 0.53, rho, ux, steps=steps)
+    assert_close(g, o, fluid_mask("d1q3", bc, nx, 1), TOL64, ("rho", "ux"), "d1q3 %d %s" % (nx, bc))
+
+
+# --------------------------------------------------------------------------
+# D2Q9, every collision rule and boundary kind, ragged sizes
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("collision", ["minxent4", "minxent2", "srt"])
+@pytest.mark.parametrize("bc", ["cavity", "periodic", "tube", "box"])
+def test_d2q9_small_fp64(collision, bc):
+    nx, ny, steps, tau = 45, 37, 30, 0.57
+    seed = 10 * ["minxent4", "minxent2", "srt"].index(collision) + ["cavity", "periodic", "tube", "box"].index(bc)
+    rho, ux, uy = smooth_fields(nx, ny, seed=seed)
+    g = gpu_run("d2q9", collision, bc, "fp64", nx, ny, tau, rho, ux, uy, steps=steps, u_lid=0.08)
+    o = orc_run("d2q9", collision, bc, nx, ny, tau, rho, ux, uy, steps=steps, u_lid=0.08)
+    assert_close(g, o, fluid_mask("d2q9", bc, nx, ny), TOL64, label="%s/%s" % (collision, bc))
+    assert g["status"]["unstable"] == o["unstable"]
+    assert g["status"]["guarded"] == o["guarded"]
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (4, 3), (3, 7), (65, 3), (300, 257)])
+def test_d2q9_edge_sizes(nx, ny):
+    rho, ux, uy = smooth_fields(nx, ny, seed=nx * 1000 + ny)
+    g = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, rho, ux, uy, steps=12, u_lid=0.1)
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=12, u_lid=0.1)
+    assert_close(g, o, fluid_mask("d2q9", "cavity", nx, ny), TOL64, label="%dx%d" % (nx, ny))
+
+
+def test_zero_steps_returns_the_initial_fields():
+    nx, ny = 70, 33
+    rho, ux, uy = smooth_fields(nx, ny, seed=5, amp=0.05)
+    g = gpu_run("d2q9", "minxent4", "periodic", "fp64", nx, ny, 0.6, rho, ux, uy, steps=0)
+    m = np.ones((ny, nx), bool)
+    # u = j / rho is recovered from populations of size ~rho/9: its absolute
+    # round-off is a few eps*rho, i.e. ~1e-15 relative to |u|max = 0.05.
+    assert_close(g, {"rho": rho, "ux": ux, "uy": uy}, m, 1e-13, label="t=0")
+
+
+def test_cavity_noise_input_matches_oracle():
+    c = I.cavity(96, 0.1, 1000.0, 1802, 200)
+    g = gpu_run("d2q9", "minxent4", "cavity", "fp64", 96, 96, c["tau"], c["rho"], c["ux"], c["uy"],
+                steps=c["steps"], u_lid=0.1)
+    o = orc_run("d2q9", "minxent4", "cavity", 96, 96, c["tau"], c["rho"], c["ux"], c["uy"], steps=c["steps"],
+                u_lid=0.1)
+    assert_close(g, o, fluid_mask("d2q9", "cavity", 96, 96), TOL64, label="cavity96")
+    assert g["status"]["guarded"] == 0 and o["guarded"] == 0
+
+
+def test_homogeneous_density_scaling_on_gpu():
+    # f -> 2 f scales every population; velocities are unchanged.
+    nx = 40
+    rho, ux, uy = smooth_fields(nx, nx, seed=9)
+    a = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, nx, 0.6, rho, ux, uy, steps=25, u_lid=0.1, rho0=1.0)
+    b = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, nx, 0.6, 2 * rho, ux, uy, steps=25, u_lid=0.1, rho0=2.0)
+    m = fluid_mask("d2q9", "cavity", nx, nx)
+    assert np.max(np.abs(b["rho"] - 2 * a["rho"])[m]) <= 1e-14
+    assert np.max(np.abs(b["ux"] - a["ux"])[m]) <= 1e-14
+
+
+# --------------------------------------------------------------------------
+# Status word
+# --------------------------------------------------------------------------
+
+def test_unstable_flag_and_first_step_match_oracle():
+    n = 16
+    z = np.zeros((n, n))
+    g = gpu_run("d2q9", "srt", "cavity", "fp64", n, n, 0.5001, np.ones((n, n)), z, z, steps=300, u_lid=0.4)
+    o = orc_run("d2q9", "srt", "cavity", n, n, 0.5001, np.ones((n, n)), z, z, steps=300, u_lid=0.4)
+    assert o["unstable"] and g["status"]["unstable"]
+    assert g["status"]["first_step"] == o["first_step"]
+
+
+def test_guarded_nodes_counted_like_oracle():
+    # A strongly perturbed start leaves p > 0 at some nodes: both count them.
+    n = 24
+    rng = np.random.default_rng(3)
+    rho = 1 + 0.6 * rng.uniform(-1, 1, (n, n))
+    ux = 0.35 * rng.uniform(-1, 1, (n, n))
+    uy = 0.35 * rng.uniform(-1, 1, (n, n))
+    g = gpu_run("d2q9", "minxent4", "periodic", "fp64", n, n, 0.52, rho, ux, uy, steps=3)
+    o = orc_run("d2q9", "minxent4", "periodic", n, n, 0.52, rho, ux, uy, steps=3)
+    assert g["status"]["guarded"] == o["guarded"]
+    assert g["status"]["unstable"] == o["unstable"]
+
+
+# --------------------------------------------------------------------------
+# Launch forms give bitwise identical results
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_newton64", "fp32", "fp16dev"])
+def test_launch_shapes_are_bitwise_identical(precision):
+    nx, ny = 300, 131
+    rho, ux, uy = smooth_fields(nx, ny, seed=11)
+    b = B()
+    ref = None
+    p = b.make_params("d2q9", "minxent4", "cavity", precision, nx, ny, 0.6, 0.0, 0.1, 1.0)
+    ctx = b.lbm_init(p, rho, ux, uy)
+    nv = b.lbm_variant_count(ctx)
+    b.lbm_free(ctx)
+    for v in range(nv):
+        g = gpu_run("d2q9", "minxent4", "cavity", precision, nx, ny, 0.6, rho, ux, uy, steps=9, u_lid=0.1,
+                    variant=v, want_f=True)
+        if ref is None:
+            ref = g["f"]
+        else:
+            assert np.array_equal(g["f"], ref), v
+
+
+def test_d1q3_launch_shapes_are_bitwise_identical():
+    nx = 5000
+    rho, ux = I.tube_fields(nx, 2.0, 0.75)
+    ref = None
+    for v in range(4):
+        g = gpu_run("d1q3", "srt", "tube", "fp64", nx, 1, 0.52, rho, ux, steps=33, variant=v, want_f=True)
+        ref = g["f"] if ref is None else ref
+        assert np.array_equal(g["f"], ref), v
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 10])
+def test_graph_replay_is_bitwise_identical(chunk):
+    nx, ny = 77, 64
+    rho, ux, uy = smooth_fields(nx, ny, seed=12)
+    a = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.58, rho, ux, uy, steps=41, u_lid=0.1,
+                want_f=True)
+    g = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.58, rho, ux, uy, steps=41, u_lid=0.1,
+                graph=chunk, want_f=True)
+    assert np.array_equal(a["f"], g["f"])
+
+
+def test_graph_replays_repeated_with_eager_work_between():
+    nx, ny = 50, 40
+    rho, ux, uy = smooth_fields(nx, ny, seed=13)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    c1 = b.lbm_init(p, rho, ux, uy)
+    c2 = b.lbm_init(p, rho, ux, uy)
+    try:
+        b.lbm_set_graph_chunk(c2, 6)
+        for k in range(5):
+            b.lbm_step(c1, 6)
+            b.lbm_step(c2, 6)
+            assert np.array_equal(b.lbm_get_populations(c1, 9), b.lbm_get_populations(c2, 9)), k
+            b.lbm_step(c1, 1)  # eager step between replays
+            b.lbm_step(c2, 1)
+        assert b.lbm_info(c2)["steps_done"] == 35
+    finally:
+        b.lbm_free(c1)
+        b.lbm_free(c2)
+
+
+def test_checkpoint_restore_is_bitwise():
+    nx, ny = 64, 48
+    rho, ux, uy = smooth_fields(nx, ny, seed=14)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    c1 = b.lbm_init(p, rho, ux, uy)
+    c2 = b.lbm_init(p, np.ones(nx * ny), np.zeros(nx * ny), np.zeros(nx * ny))
+    try:
+        b.lbm_step(c1, 10)
+        b.lbm_set_populations(c2, b.lbm_get_populations(c1, 9))
+        b.lbm_step(c1, 15)
+        b.lbm_step(c2, 15)
+        assert np.array_equal(b.lbm_get_populations(c1, 9), b.lbm_get_populations(c2, 9))
+    finally:
+        b.lbm_free(c1)
+        b.lbm_free(c2)
+
+
+def test_autotune_keeps_the_state_and_caches(tmp_path):
+    nx, ny = 200, 150
+    rho, ux, uy = smooth_fields(nx, ny, seed=15)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    c1 = b.lbm_init(p, rho, ux, uy)
+    c2 = b.lbm_init(p, rho, ux, uy)
+    cache = str(tmp_path / "tune.txt")
+    try:
+        b.lbm_step(c1, 5)
+        b.lbm_step(c2, 5)
+        v = b.lbm_autotune(c2, cache)
+        assert 0 <= v < b.lbm_variant_count(c2)
+        assert b.lbm_autotune(c2, cache) == v  # second call reads the cache
+        b.lbm_step(c1, 5)
+        b.lbm_step(c2, 5)
+        assert np.array_equal(b.lbm_get_populations(c1, 9), b.lbm_get_populations(c2, 9))
+        assert not b.lbm_status(c2)["unstable"]
+    finally:
+        b.lbm_free(c1)
+        b.lbm_free(c2)
+
+
+def test_caller_workspace_and_stream():
+    import torch
+    nx, ny = 60, 50
+    rho, ux, uy = smooth_fields(nx, ny, seed=16)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    ws = torch.empty(b.lbm_workspace_bytes(p), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    ctx = b.lbm_init(p, rho, ux, uy, workspace=ws, stream=s)
+    try:
+        b.lbm_step(ctx, 20)
+        r, u, v = b.lbm_moments(ctx)
+    finally:
+        b.lbm_free(ctx)
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=20, u_lid=0.1)
+    g = {"rho": r.reshape(ny, nx), "ux": u.reshape(ny, nx), "uy": v.reshape(ny, nx)}
+    assert_close(g, o, fluid_mask("d2q9", "cavity", nx, ny), TOL64, label="caller ws")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(b.LbmError):
+        b.lbm_init(p, rho, ux, uy, workspace=small)
+
+
+def test_copy_kernel():
+    import torch
+    b = B()
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    b.lbm_copy_kernel(dst, src, src.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
