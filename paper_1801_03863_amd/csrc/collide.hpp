@@ -23,12 +23,11 @@
 //   f0 = feq + (1 - 1/tau) [ (P_xx-yy - rho(ux^2-uy^2)) T^-1_col8 + (P_xy - rho ux uy) T^-1_col9 ]
 // with T^-1_col8 = (0,1,-1,1,-1,0,0,0,0)/4 and T^-1_col9 = (0,0,0,0,0,1,-1,1,-1)/4.
 //
-// Two evaluations of g:
-//   PRODUCT  (double): g is the log of a product of population ratios that
-//            are each close to one, four logarithms per node;
-//   DEVIATION (float): f0_a = W_a rho (1 + e_a) with e_a built from small
-//            terms only, and ln(f0_a/W_a) = ln rho + log1p(e_a); nine log1p
-//            per node, no cancellation in single precision.
+// The gradient is evaluated as the logarithms of four products of population
+// ratios f0_a / f0_b, each close to one near equilibrium (four logarithms per
+// node instead of nine).  In single precision this is as accurate as taking
+// the nine logarithms of the deviations from the weights; both are limited
+// by the single-precision start point.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,14 +51,38 @@ __device__ __forceinline__ double rcp(double x)
     return r;
 }
 
-__device__ __forceinline__ float rcp(float x)
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Natural logarithm of a positive finite double.  Argument reduction
+// y = m 2^k with m in [sqrt(1/2), sqrt(2)), then ln m = 2 atanh(s) with
+// s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd series through s^19
+// (truncation below 2^-54), and k ln 2 added with ln 2 split into a 32-bit
+// head and a tail (the Cody-Waite / fdlibm split).  Error <= 2-3 ulp.
+__device__ __forceinline__ double ln(double y)
 {
-    float r = __builtin_amdgcn_rcpf(x);
-    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+    double m = __builtin_amdgcn_frexp_mant(y);  // [0.5, 1)
+    int k = __builtin_amdgcn_frexp_exp(y);
+    const bool lo = m < 0.70710678118654752440;
+    m = lo ? m + m : m;
+    k = lo ? k - 1 : k;
+    const double s = (m - 1.0) * rcp(m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = __builtin_fma(p, z, 1.0 / 17.0);
+    p = __builtin_fma(p, z, 1.0 / 15.0);
+    p = __builtin_fma(p, z, 1.0 / 13.0);
+    p = __builtin_fma(p, z, 1.0 / 11.0);
+    p = __builtin_fma(p, z, 1.0 / 9.0);
+    p = __builtin_fma(p, z, 1.0 / 7.0);
+    p = __builtin_fma(p, z, 1.0 / 5.0);
+    p = __builtin_fma(p, z, 1.0 / 3.0);
+    const double t = s + s;
+    const double lnm = __builtin_fma(t * z, p, t);
+    const double kd = (double)k;
+    return __builtin_fma(kd, 6.93147180369123816490e-01, __builtin_fma(kd, 1.90821492927058770002e-10, lnm));
 }
 
-__device__ __forceinline__ double ln(double x) { return log(x); }
-__device__ __forceinline__ float ln1p(float x) { return log1pf(x); }
+__device__ __forceinline__ float ln(float y) { return logf(y); }
 
 template <class C>
 __device__ __forceinline__ bool positive_finite(C v)
@@ -143,11 +166,11 @@ __device__ __forceinline__ void collide_srt(C (&f)[9], C omega)
 }
 
 // MinxEnt collision with a single Newton step.  MX2 selects MinxEnt2 (only
-// e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).  DEVLOG selects the
-// deviation evaluation of the gradient (see the file comment).  Returns true
+// e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).
+// Returns true
 // if the node was guarded: its start point had a population <= 0 or not
 // finite, in which case f holds the start point itself (no Newton step).
-template <class C, bool DEVLOG, bool MX2>
+template <class C, bool MX2>
 __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
 {
     // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C).
@@ -214,29 +237,14 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
 #pragma unroll
     for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
 
-    // Gradient g = A^T ln(f0 / W).
+    // Gradient g = A^T ln(f0 / W), as logarithms of products of ratios:
+    //  g_e   = ln( 2^24 (f5 f6 f7 f8)^2 r0^4 r1 r2 r3 r4 )
+    //  g_eps = ln( f0^4 f5 f6 f7 f8 (r1 r2 r3 r4)^2 )
+    //  g_qx  = ln( (f3 r1)^2 f5 f8 r6 r7 ),  g_qy = ln( (f4 r2)^2 f5 f6 r7 r8 )
+    // with r_a = 1/f0_a (2^24 = prod_a W_a^(-a_e,a), the only non-zero weight
+    // term; ln rho and the "+1" cancel because the columns sum to zero).
     C g[4];
-    if (DEVLOG) {
-        // e_a + c_a / (W_a rho): the full relative deviation of f0_a.
-        C L[9];
-        const C ia = irho * C(9), id = irho * C(36);
-        L[0] = ln1p(e[0]);
-#pragma unroll
-        for (int a = 1; a < 5; ++a) L[a] = ln1p(e[a] + c[a] * ia);
-#pragma unroll
-        for (int a = 5; a < 9; ++a) L[a] = ln1p(e[a] + c[a] * id);
-        const C La = (L[1] + L[2]) + (L[3] + L[4]);
-        const C Ld = (L[5] + L[6]) + (L[7] + L[8]);
-        g[0] = C(2) * Ld - La - C(4) * L[0];
-        g[1] = Ld - C(2) * La + C(4) * L[0];
-        g[2] = C(2) * (L[3] - L[1]) + (L[5] + L[8]) - (L[6] + L[7]);
-        g[3] = C(2) * (L[4] - L[2]) + (L[5] + L[6]) - (L[7] + L[8]);
-    } else {
-        // Products of ratios, each near one at equilibrium:
-        //  g_e   = ln( 2^24 (f5 f6 f7 f8)^2 r0^4 r1 r2 r3 r4 )
-        //  g_eps = ln( f0^4 f5 f6 f7 f8 (r1 r2 r3 r4)^2 )
-        //  g_qx  = ln( (f3 r1)^2 f5 f8 r6 r7 ),  g_qy = ln( (f4 r2)^2 f5 f6 r7 r8 )
-        // (2^24 = prod W_a^(-a_e,a), the only non-zero weight term).
+    {
         const C X = ((f0[5] * r[1]) * (f0[6] * r[2])) * ((f0[7] * r[3]) * (f0[8] * r[4]));
         const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
         const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));

@@ -30,10 +30,10 @@ namespace lbm {
 // --------------------------------------------------------------------------
 
 template <int ST> struct Form;
-template <> struct Form<ST_F64> { using T = double; using C = double; static constexpr bool DEVLOG = false; };
-template <> struct Form<ST_F32N64> { using T = float; using C = double; static constexpr bool DEVLOG = false; };
-template <> struct Form<ST_F32> { using T = float; using C = float; static constexpr bool DEVLOG = true; };
-template <> struct Form<ST_F16DEV> { using T = _Float16; using C = float; static constexpr bool DEVLOG = true; };
+template <> struct Form<ST_F64> { using T = double; using C = double; };
+template <> struct Form<ST_F32N64> { using T = float; using C = double; };
+template <> struct Form<ST_F32> { using T = float; using C = float; };
+template <> struct Form<ST_F16DEV> { using T = _Float16; using C = float; };
 
 template <int ST>
 __device__ __forceinline__ typename Form<ST>::C load(const typename Form<ST>::T *p, typename Form<ST>::C ref,
@@ -142,7 +142,7 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
     if constexpr (CO == CO_SRT) {
         collide_srt<C>(f, C(in.omega));
     } else {
-        const bool g = collide_minxent<C, Form<ST>::DEVLOG, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2));
+        const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2));
         flags |= g ? 2 : 0;
     }
     bool ok = true;
@@ -541,7 +541,6 @@ hipError_t dispatch9c(int coll, int v, const void *src, void *dst, const StepArg
     }
 }
 
-constexpr int kBatchBlocks[] = {256, 128};
 
 template <int ST, int CO>
 hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)

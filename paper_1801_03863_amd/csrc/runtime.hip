@@ -431,20 +431,27 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
 
 extern "C" {
 
+static int ws_bytes(const lbm_params_t *p, int32_t n, size_t *bytes)
+{
+    if (!bytes) return fail(LBM_EINVAL, "null output pointer");
+    int64_t elems, nodes;
+    layout(p, n, p[0].lattice == LBM_D1Q3 ? 3 : 9, nullptr, &elems, &nodes);
+    *bytes = 2 * buffer_bytes(elems, elem_bytes(p[0].precision));
+    return LBM_OK;
+}
+
 int lbm_workspace_bytes(const lbm_params_t *p, size_t *bytes)
 {
-    return lbm_workspace_bytes_batch(p, 1, bytes);
+    int rc = check_params(p);
+    if (rc) return rc;
+    return ws_bytes(p, 1, bytes);
 }
 
 int lbm_workspace_bytes_batch(const lbm_params_t *p, int32_t n, size_t *bytes)
 {
     int rc = check_batch(p, n);
     if (rc) return rc;
-    if (!bytes) return fail(LBM_EINVAL, "null output pointer");
-    int64_t elems, nodes;
-    layout(p, n, p[0].lattice == LBM_D1Q3 ? 3 : 9, nullptr, &elems, &nodes);
-    *bytes = 2 * buffer_bytes(elems, elem_bytes(p[0].precision));
-    return LBM_OK;
+    return ws_bytes(p, n, bytes);
 }
 
 int lbm_init(const lbm_params_t *p, const double *rho, const double *ux, const double *uy, void *ws,

@@ -76,3 +76,10 @@ def test_batch_must_share_forms(B):
 
 def test_error_strings(B):
     assert B._lib.lbm_strerror(B.LBM_EINVAL) == b"invalid argument"
+
+
+def test_single_lattice_workspace_has_no_batch_size_limit(B):
+    p = B.make_params("d2q9", "minxent4", "cavity", "fp32_newton64", 8192, 8192, 0.6)
+    assert B.lbm_workspace_bytes(p) == 2 * 9 * 8192 * 8192 * 4
+    with pytest.raises(B.LbmError):
+        B.lbm_workspace_bytes_batch([p])
