@@ -53,9 +53,11 @@ enum { LBM_D1Q3 = 1, LBM_D2Q9 = 2 };
 /* Collision rule of fluid nodes.  MINXENT4 is the paper's MinxEnt with five
  * constraints and four free moments (Sec. IV.C-D); MINXENT2 adds the two
  * constraints C5, C7 relaxed with tau2 (two free moments).  SRT is the BGK
- * rule of Sec. II.B.1.  On D1Q3 every rule is SRT: with mass, momentum and
- * the relaxed second moment fixed no moment is left to minimise over. */
-enum { LBM_MINXENT4 = 0, LBM_MINXENT2 = 1, LBM_SRT = 2 };
+ * rule of Sec. II.B.1.  TRT and MRT are the comparator rules of Sec. II.B.2
+ * with the relaxation rates of Table III (tau2 as for MINXENT2).  On D1Q3
+ * every rule is SRT: with mass, momentum and the relaxed second moment fixed
+ * no moment is left to minimise over. */
+enum { LBM_MINXENT4 = 0, LBM_MINXENT2 = 1, LBM_SRT = 2, LBM_TRT = 3, LBM_MRT = 4 };
 
 /* Boundary kinds (Sec. IV.E): full-way bounce-back walls and an equilibrium
  * moving wall.
@@ -71,23 +73,25 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_TUBE = 1, LBM_BC_CAVITY = 2, LBM_BC_BOX = 3 }
  *   FP64:          populations stored and computed in double.
  *   FP32_NEWTON64: populations stored in float, every node computed in
  *                  double (moments, logarithms, Newton step, correction).
- *   FP32:          stored and computed in float; the logarithms are taken of
- *                  the small deviations from the weights (log1p), so the
- *                  gradient does not cancel.
+ *   FP32:          stored and computed in float (the four logarithms of the
+ *                  gradient are taken of products of population ratios that
+ *                  are each close to one).
  *   FP16DEV:       stored as binary16 deviations (f_i - W_i rho0) * 2^k,
- *                  computed in float as FP32. */
+ *                  computed in float as FP32.  The reference density rho0
+ *                  is per instance; a deviation beyond 65504 * 2^-k overflows
+ *                  to inf and sets UNSTABLE. */
 enum { LBM_FP64 = 0, LBM_FP32_NEWTON64 = 1, LBM_FP32 = 2, LBM_FP16DEV = 3 };
 
 typedef struct lbm_params {
     int32_t lattice;    /* LBM_D1Q3 or LBM_D2Q9 */
-    int32_t collision;  /* LBM_MINXENT4, LBM_MINXENT2 or LBM_SRT */
+    int32_t collision;  /* LBM_MINXENT4, LBM_MINXENT2, LBM_SRT, LBM_TRT or LBM_MRT */
     int32_t bc;         /* LBM_BC_* */
     int32_t precision;  /* LBM_FP64, LBM_FP32_NEWTON64, LBM_FP32, LBM_FP16DEV */
     int32_t nx, ny;     /* nodes per axis, boundary nodes included; ny = 1 for D1Q3 */
-    int32_t fp16_exp;   /* FP16DEV scale exponent k (0 selects 16); ignored otherwise */
+    int32_t fp16_exp;   /* FP16DEV scale exponent k (0 selects 14: |f_i - W_i rho0| < 4); ignored otherwise */
     int32_t reserved;   /* must be 0 */
     double tau;         /* relaxation time, > 1/2; nu = (2 tau - 1)/6 (Sec. IV.C) */
-    double tau2;        /* MINXENT2 only; <= 0 selects (8 tau - 1)/(2 tau - 1) (Sec. IV.C) */
+    double tau2;        /* MINXENT2, TRT, MRT; <= 0 selects (8 tau - 1)/(2 tau - 1) (Sec. IV.C) */
     double u_lid;       /* lid x-velocity for LBM_BC_CAVITY */
     double rho0;        /* lid density, and the FP16DEV reference density */
 } lbm_params_t;

@@ -27,14 +27,15 @@ _lib = ctypes.CDLL(LIB_PATH)
 # Enumerations of lbm.h.
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ENODEV = 0, -1, -2, -3, -4
 LBM_D1Q3, LBM_D2Q9 = 1, 2
-LBM_MINXENT4, LBM_MINXENT2, LBM_SRT = 0, 1, 2
+LBM_MINXENT4, LBM_MINXENT2, LBM_SRT, LBM_TRT, LBM_MRT = 0, 1, 2, 3, 4
 LBM_BC_PERIODIC, LBM_BC_TUBE, LBM_BC_CAVITY, LBM_BC_BOX = 0, 1, 2, 3
 LBM_FP64, LBM_FP32_NEWTON64, LBM_FP32, LBM_FP16DEV = 0, 1, 2, 3
 STATUS_UNSTABLE, STATUS_GUARDED = 1, 2
 
 _NAMES = {
     "lattice": {"d1q3": LBM_D1Q3, "d2q9": LBM_D2Q9},
-    "collision": {"minxent4": LBM_MINXENT4, "minxent2": LBM_MINXENT2, "srt": LBM_SRT},
+    "collision": {"minxent4": LBM_MINXENT4, "minxent2": LBM_MINXENT2, "srt": LBM_SRT, "trt": LBM_TRT,
+                  "mrt": LBM_MRT},
     "bc": {"periodic": LBM_BC_PERIODIC, "tube": LBM_BC_TUBE, "cavity": LBM_BC_CAVITY, "box": LBM_BC_BOX},
     "precision": {"fp64": LBM_FP64, "fp32_newton64": LBM_FP32_NEWTON64, "fp32": LBM_FP32,
                   "fp16dev": LBM_FP16DEV},

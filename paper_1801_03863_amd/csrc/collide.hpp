@@ -53,36 +53,84 @@ __device__ __forceinline__ double rcp(double x)
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Natural logarithm of a positive finite double.  Argument reduction
+// One Newton refinement of the hardware reciprocal (v_rcp_f64 is good to
+// about 4.6e-8 relative; one step brings it to about 2e-15).
+__device__ __forceinline__ double rcp1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+}
+
+__device__ __forceinline__ float rcp1(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Reciprocals of N positive values with a single hardware reciprocal
+// (Montgomery's simultaneous inversion): prefix products, one full-precision
+// reciprocal of the total, then back-substitution.  The caller guarantees
+// the total product is a positive normal number.
+template <int N>
+__device__ __forceinline__ void batch_rcp(const double (&x)[N], double (&r)[N], double &prod)
+{
+    double p[N];
+    p[0] = x[0];
+#pragma unroll
+    for (int i = 1; i < N; ++i) p[i] = p[i - 1] * x[i];
+    prod = p[N - 1];
+    double q = rcp(p[N - 1]);
+#pragma unroll
+    for (int i = N - 1; i > 0; --i) {
+        r[i] = q * p[i - 1];
+        q = q * x[i];
+    }
+    r[0] = q;
+}
+
+// Natural logarithms of four positive finite doubles.  Argument reduction
 // y = m 2^k with m in [sqrt(1/2), sqrt(2)), then ln m = 2 atanh(s) with
 // s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd series through s^19
 // (truncation below 2^-54), and k ln 2 added with ln 2 split into a 32-bit
-// head and a tail (the Cody-Waite / fdlibm split).  Error <= 2-3 ulp.
-__device__ __forceinline__ double ln(double y)
+// head and a tail (the Cody-Waite / fdlibm split).  The four divisions share
+// one reciprocal.  Error <= 2-3 ulp.
+__device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
 {
-    double m = __builtin_amdgcn_frexp_mant(y);  // [0.5, 1)
-    int k = __builtin_amdgcn_frexp_exp(y);
-    const bool lo = m < 0.70710678118654752440;
-    m = lo ? m + m : m;
-    k = lo ? k - 1 : k;
-    const double s = (m - 1.0) * rcp(m + 1.0);
-    const double z = s * s;
-    double p = 1.0 / 19.0;
-    p = __builtin_fma(p, z, 1.0 / 17.0);
-    p = __builtin_fma(p, z, 1.0 / 15.0);
-    p = __builtin_fma(p, z, 1.0 / 13.0);
-    p = __builtin_fma(p, z, 1.0 / 11.0);
-    p = __builtin_fma(p, z, 1.0 / 9.0);
-    p = __builtin_fma(p, z, 1.0 / 7.0);
-    p = __builtin_fma(p, z, 1.0 / 5.0);
-    p = __builtin_fma(p, z, 1.0 / 3.0);
-    const double t = s + s;
-    const double lnm = __builtin_fma(t * z, p, t);
-    const double kd = (double)k;
-    return __builtin_fma(kd, 6.93147180369123816490e-01, __builtin_fma(kd, 1.90821492927058770002e-10, lnm));
+    double m[4], den[4], rd[4], kd[4], prod;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double mi = __builtin_amdgcn_frexp_mant(y[i]);  // [0.5, 1)
+        int k = __builtin_amdgcn_frexp_exp(y[i]);
+        const bool lo = mi < 0.70710678118654752440;
+        mi = lo ? mi + mi : mi;
+        kd[i] = (double)(lo ? k - 1 : k);
+        m[i] = mi;
+        den[i] = mi + 1.0;
+    }
+    batch_rcp<4>(den, rd, prod);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double s = (m[i] - 1.0) * rd[i];
+        const double z = s * s;
+        double p = 1.0 / 19.0;
+        p = __builtin_fma(p, z, 1.0 / 17.0);
+        p = __builtin_fma(p, z, 1.0 / 15.0);
+        p = __builtin_fma(p, z, 1.0 / 13.0);
+        p = __builtin_fma(p, z, 1.0 / 11.0);
+        p = __builtin_fma(p, z, 1.0 / 9.0);
+        p = __builtin_fma(p, z, 1.0 / 7.0);
+        p = __builtin_fma(p, z, 1.0 / 5.0);
+        p = __builtin_fma(p, z, 1.0 / 3.0);
+        const double t = s + s;
+        const double lnm = __builtin_fma(t * z, p, t);
+        out[i] = __builtin_fma(kd[i], 6.93147180369123816490e-01,
+                               __builtin_fma(kd[i], 1.90821492927058770002e-10, lnm));
+    }
 }
 
-__device__ __forceinline__ float ln(float y) { return logf(y); }
+__device__ __forceinline__ void ln4(const float (&y)[4], float (&out)[4])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = logf(y[i]);
+}
+
+
 
 template <class C>
 __device__ __forceinline__ bool positive_finite(C v)
@@ -127,15 +175,15 @@ struct Sym4 {
 template <class C>
 __device__ __forceinline__ void ldlt_solve4(const Sym4<C> &h, C (&g)[4])
 {
-    const C d0 = h.ee, i0 = rcp(d0);
+    const C d0 = h.ee, i0 = rcp1(d0);
     const C l10 = h.ep * i0, l20 = h.ex * i0, l30 = h.ey * i0;
-    const C d1 = h.pp - l10 * h.ep, i1 = rcp(d1);
+    const C d1 = h.pp - l10 * h.ep, i1 = rcp1(d1);
     const C t21 = h.px - l20 * h.ep, t31 = h.py - l30 * h.ep;
     const C l21 = t21 * i1, l31 = t31 * i1;
-    const C d2 = h.xx - l20 * h.ex - l21 * t21, i2 = rcp(d2);
+    const C d2 = h.xx - l20 * h.ex - l21 * t21, i2 = rcp1(d2);
     const C t32 = h.xy - l30 * h.ex - l31 * t21;
     const C l32 = t32 * i2;
-    const C d3 = h.yy - l30 * h.ey - l31 * t31 - l32 * t32, i3 = rcp(d3);
+    const C d3 = h.yy - l30 * h.ey - l31 * t31 - l32 * t32, i3 = rcp1(d3);
     // forward (unit lower), diagonal, backward
     const C z0 = g[0];
     const C z1 = g[1] - l10 * z0;
@@ -163,6 +211,43 @@ __device__ __forceinline__ void collide_srt(C (&f)[9], C omega)
     equilibrium(rho, jx * irho, jy * irho, feq);
 #pragma unroll
     for (int a = 0; a < 9; ++a) f[a] = f[a] + omega * (feq[a] - f[a]);
+}
+
+// Multiple-relaxation-time rule (Sec. II.B.2): f += T^-1 B T (feq - f) with
+// B diagonal (Table III).  The conserved rows have rate 0; be, bp relax the
+// energy-like rows e and eps, bq the heat-flux rows q_x, q_y, bs the two
+// stress rows.  TRT is be = bp = bs = 1/tau, bq = 1/tau2; MRT is be = 1.64,
+// bp = 1.54, bq = 1/tau2, bs = 1/tau.  T^-1 = T^T diag(1/|row|^2).
+template <class C>
+__device__ __forceinline__ void collide_mrt(C (&f)[9], C be, C bp, C bq, C bs)
+{
+    const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const C irho = rcp(rho);
+    C d[9];
+    equilibrium(rho, jx * irho, jy * irho, d);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = d[a] - f[a];
+    const C da = (d[1] + d[2]) + (d[3] + d[4]);
+    const C dd = (d[5] + d[6]) + (d[7] + d[8]);
+    const C se = be * C(1.0 / 36.0) * ((C(2) * dd - da) - C(4) * d[0]);
+    const C sp = bp * C(1.0 / 36.0) * ((dd - C(2) * da) + C(4) * d[0]);
+    const C sx = bq * C(1.0 / 12.0) * (C(2) * (d[3] - d[1]) + (d[5] + d[8]) - (d[6] + d[7]));
+    const C sy = bq * C(1.0 / 12.0) * (C(2) * (d[4] - d[2]) + (d[5] + d[6]) - (d[7] + d[8]));
+    const C s8 = bs * C(0.25) * ((d[1] + d[3]) - (d[2] + d[4]));
+    const C s9 = bs * C(0.25) * ((d[5] + d[7]) - (d[6] + d[8]));
+    const C axis = -(se + C(2) * sp);
+    const C dgn = C(2) * se + sp;
+    f[0] = f[0] + C(4) * (sp - se);
+    f[1] = f[1] + ((axis - C(2) * sx) + s8);
+    f[2] = f[2] + ((axis - C(2) * sy) - s8);
+    f[3] = f[3] + ((axis + C(2) * sx) + s8);
+    f[4] = f[4] + ((axis + C(2) * sy) - s8);
+    f[5] = f[5] + ((dgn + (sx + sy)) + s9);
+    f[6] = f[6] + ((dgn - (sx - sy)) - s9);
+    f[7] = f[7] + ((dgn - (sx + sy)) + s9);
+    f[8] = f[8] + ((dgn + (sx - sy)) - s9);
 }
 
 // MinxEnt collision with a single Newton step.  MX2 selects MinxEnt2 (only
@@ -225,17 +310,31 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
 #pragma unroll
     for (int a = 5; a < 9; ++a) f0[a] = (wd + wd * e[a]) + c[a];
 
-    bool ok = true;
+    // Guard: every start population positive and finite.  The minimum
+    // catches values <= 0; the product (double) or sum (float) is not finite
+    // if any value is inf or NaN.
+    C mn = f0[0];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) ok = ok && positive_finite(f0[a]);
+    for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f0[a]);
+    C r[9];
+    bool ok;
+    if constexpr (sizeof(C) == 8) {
+        double prod;
+        batch_rcp<9>(f0, r, prod);
+        ok = mn > C(0) && prod > 2.2250738585072014e-308 && prod < C(__builtin_huge_val());
+    } else {
+        C sum = f0[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) sum += f0[a];
+        ok = mn > C(0) && sum < C(__builtin_huge_valf());
+#pragma unroll
+        for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
+    }
     if (!ok) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) f[a] = f0[a];
         return true;
     }
-    C r[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
 
     // Gradient g = A^T ln(f0 / W), as logarithms of products of ratios:
     //  g_e   = ln( 2^24 (f5 f6 f7 f8)^2 r0^4 r1 r2 r3 r4 )
@@ -249,10 +348,12 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
         const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
         const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));
         const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        g[0] = ln((Pe * X) * C(16777216.0));
-        g[1] = ln(Pp * X);
-        g[2] = ln((t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7])));
-        g[3] = ln((t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8])));
+        C y[4];
+        y[0] = (Pe * X) * C(16777216.0);
+        y[1] = Pp * X;
+        y[2] = (t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7]));
+        y[3] = (t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8]));
+        ln4(y, g);
     }
 
     // Hessian H = A^T diag(r) A.
@@ -267,7 +368,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
     if (MX2) {
         // Two free moments: closed-form 2 x 2 solve.
         const C det = h.ee * h.pp - h.ep * h.ep;
-        const C idet = rcp(det);
+        const C idet = rcp1(det);
         de = (h.pp * g[0] - h.ep * g[1]) * idet;
         dp = (h.ee * g[1] - h.ep * g[0]) * idet;
     } else {

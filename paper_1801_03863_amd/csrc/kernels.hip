@@ -102,22 +102,44 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
     }
 }
 
-// Pull the nine populations that stream into node (x, y).
+// Pull the nine populations that stream into node (x, y).  Plane bases are
+// uniform (scalar registers); per-lane addressing is one 32-bit byte offset
+// per row/column combination, so loads use the scalar-base + vector-offset
+// form.
 template <int ST>
 __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
                                       const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
                                       typename Form<ST>::C (&f)[9])
 {
-    const int rc = y * nx, rm = n.ym * nx, rp = n.yp * nx;
-    f[0] = load<ST>(s + rc + x, ref[0], iscale);
-    f[1] = load<ST>(s + P + rc + n.xm, ref[1], iscale);
-    f[2] = load<ST>(s + 2 * P + rm + x, ref[2], iscale);
-    f[3] = load<ST>(s + 3 * P + rc + n.xp, ref[3], iscale);
-    f[4] = load<ST>(s + 4 * P + rp + x, ref[4], iscale);
-    f[5] = load<ST>(s + 5 * P + rm + n.xm, ref[5], iscale);
-    f[6] = load<ST>(s + 6 * P + rm + n.xp, ref[6], iscale);
-    f[7] = load<ST>(s + 7 * P + rp + n.xp, ref[7], iscale);
-    f[8] = load<ST>(s + 8 * P + rp + n.xm, ref[8], iscale);
+    using T = typename Form<ST>::T;
+    const char *b = (const char *)s;
+    const int64_t PB = P * (int64_t)sizeof(T);
+    const uint32_t E = sizeof(T);
+    const uint32_t rc = (uint32_t)(y * nx) * E, rm = (uint32_t)(n.ym * nx) * E, rp = (uint32_t)(n.yp * nx) * E;
+    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
+    f[0] = load<ST>((const T *)(b + (rc + cc)), ref[0], iscale);
+    f[1] = load<ST>((const T *)(b + PB + (rc + cm)), ref[1], iscale);
+    f[2] = load<ST>((const T *)(b + 2 * PB + (rm + cc)), ref[2], iscale);
+    f[3] = load<ST>((const T *)(b + 3 * PB + (rc + cp)), ref[3], iscale);
+    f[4] = load<ST>((const T *)(b + 4 * PB + (rp + cc)), ref[4], iscale);
+    f[5] = load<ST>((const T *)(b + 5 * PB + (rm + cm)), ref[5], iscale);
+    f[6] = load<ST>((const T *)(b + 6 * PB + (rm + cp)), ref[6], iscale);
+    f[7] = load<ST>((const T *)(b + 7 * PB + (rp + cp)), ref[7], iscale);
+    f[8] = load<ST>((const T *)(b + 8 * PB + (rp + cm)), ref[8], iscale);
+}
+
+// Write the nine post-collision populations of node index i.
+template <int ST>
+__device__ __forceinline__ void push9(typename Form<ST>::T *__restrict__ d, int64_t P, int i,
+                                      const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
+                                      float scale)
+{
+    using T = typename Form<ST>::T;
+    char *b = (char *)d;
+    const int64_t PB = P * (int64_t)sizeof(T);
+    const uint32_t o = (uint32_t)i * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) store<ST>((T *)(b + q * PB + o), f[q], ref[q], scale);
 }
 
 // Role collision of one D2Q9 node.  Returns bit 0 = unstable, bit 1 = guarded.
@@ -141,13 +163,23 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
     int flags = 0;
     if constexpr (CO == CO_SRT) {
         collide_srt<C>(f, C(in.omega));
+    } else if constexpr (CO == CO_TRT) {
+        collide_mrt<C>(f, C(in.omega), C(in.omega), C(in.omega2), C(in.omega));
+    } else if constexpr (CO == CO_MRT) {
+        collide_mrt<C>(f, C(1.64), C(1.54), C(in.omega2), C(in.omega));
     } else {
         const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2));
         flags |= g ? 2 : 0;
     }
-    bool ok = true;
+    // Stable iff every population is >= 0 and finite: the minimum catches
+    // negatives, the sum catches inf and NaN.
+    C mn = f[0], sm = f[0];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) ok = ok && nonneg_finite(f[a]);
+    for (int a = 1; a < 9; ++a) {
+        mn = __builtin_fmin(mn, f[a]);
+        sm += f[a];
+    }
+    const bool ok = mn >= C(0) && sm < C(__builtin_huge_valf());
     return flags | (ok ? 0 : 1);
 }
 
@@ -211,11 +243,7 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
         const int fl = node9<ST, CO>(f, role, in);
         bad = bad || (xin && (fl & 1));
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) {
-            typename Form<ST>::T *d = dst + y * nx + x;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) store<ST>(d + q * P, f[q], ref[q], a.fp16_scale);
-        }
+        if (xin) push9<ST>(dst, P, y * nx + x, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -253,11 +281,7 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     pull9<ST>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
     const int role = role9(x, y, nx, ny, a.bc);
     const int fl = node9<ST, CO>(f, role, in);
-    if (valid) {
-        typename Form<ST>::T *d = dst + in.offset + node;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) store<ST>(d + q * P, f[q], ref[q], a.fp16_scale);
-    }
+    if (valid) push9<ST>(dst + in.offset, P, node, f, ref, a.fp16_scale);
     const int guarded = __popcll(__ballot(valid && (fl & 2)));
     report(a.status + i, valid && (fl & 1), guarded, a.step, a.step_base);
 }
@@ -537,6 +561,8 @@ hipError_t dispatch9c(int coll, int v, const void *src, void *dst, const StepArg
     case CO_MINXENT4: return dispatch9<ST, CO_MINXENT4>(v, src, dst, a, s);
     case CO_MINXENT2: return dispatch9<ST, CO_MINXENT2>(v, src, dst, a, s);
     case CO_SRT: return dispatch9<ST, CO_SRT>(v, src, dst, a, s);
+    case CO_TRT: return dispatch9<ST, CO_TRT>(v, src, dst, a, s);
+    case CO_MRT: return dispatch9<ST, CO_MRT>(v, src, dst, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -560,6 +586,8 @@ hipError_t dispatch9bc(int coll, int v, const void *src, void *dst, const StepAr
     case CO_MINXENT4: return dispatch9b<ST, CO_MINXENT4>(v, src, dst, a, s);
     case CO_MINXENT2: return dispatch9b<ST, CO_MINXENT2>(v, src, dst, a, s);
     case CO_SRT: return dispatch9b<ST, CO_SRT>(v, src, dst, a, s);
+    case CO_TRT: return dispatch9b<ST, CO_TRT>(v, src, dst, a, s);
+    case CO_MRT: return dispatch9b<ST, CO_MRT>(v, src, dst, a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -8,7 +8,7 @@
 namespace lbm {
 
 enum Storage { ST_F64 = 0, ST_F32N64 = 1, ST_F32 = 2, ST_F16DEV = 3 };
-enum Coll { CO_MINXENT4 = 0, CO_MINXENT2 = 1, CO_SRT = 2 };
+enum Coll { CO_MINXENT4 = 0, CO_MINXENT2 = 1, CO_SRT = 2, CO_TRT = 3, CO_MRT = 4 };
 enum Bc { BC_PERIODIC = 0, BC_TUBE = 1, BC_CAVITY = 2, BC_BOX = 3 };
 
 // Status record of one instance (device memory).

@@ -67,7 +67,7 @@ int check_params(const lbm_params_t *p)
 {
     if (!p) return fail(LBM_EINVAL, "null parameters");
     if (p->lattice != LBM_D1Q3 && p->lattice != LBM_D2Q9) return fail(LBM_EINVAL, "lattice must be D1Q3 or D2Q9");
-    if (p->collision < LBM_MINXENT4 || p->collision > LBM_SRT) return fail(LBM_EINVAL, "unknown collision rule");
+    if (p->collision < LBM_MINXENT4 || p->collision > LBM_MRT) return fail(LBM_EINVAL, "unknown collision rule");
     if (p->bc < LBM_BC_PERIODIC || p->bc > LBM_BC_BOX) return fail(LBM_EINVAL, "unknown boundary kind");
     if (p->precision < LBM_FP64 || p->precision > LBM_FP16DEV) return fail(LBM_EINVAL, "unknown precision form");
     if (p->nx < 3) return fail(LBM_EINVAL, "nx must be >= 3");
@@ -76,7 +76,7 @@ int check_params(const lbm_params_t *p)
     if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)0x7fffffff / 2)
         return fail(LBM_EINVAL, "lattice too large for one instance (nx*ny must be < 2^30)");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be finite and > 1/2");
-    if (p->collision == LBM_MINXENT2 && p->tau2 > 0.0 && !(p->tau2 > 0.5 && std::isfinite(p->tau2)))
+    if (p->tau2 > 0.0 && !(p->tau2 > 0.5 && std::isfinite(p->tau2)))
         return fail(LBM_EINVAL, "tau2 must be finite and > 1/2 (or <= 0 for the default)");
     if (!std::isfinite(p->u_lid)) return fail(LBM_EINVAL, "u_lid must be finite");
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be finite and > 0");
@@ -176,8 +176,6 @@ int check_batch(const lbm_params_t *p, int32_t n)
             return fail(LBM_EINVAL, "batch instances must share lattice, collision, bc, precision and fp16_exp");
         if ((int64_t)p[i].nx * (p[i].lattice == LBM_D1Q3 ? 1 : p[i].ny) > kMaxBatchNodes)
             return fail(LBM_EINVAL, "batched instances are limited to 2^22 nodes each");
-        if (p[i].rho0 != p[0].rho0 && p[i].precision == LBM_FP16DEV)
-            return fail(LBM_EINVAL, "FP16DEV batch instances must share rho0");
     }
     return LBM_OK;
 }
@@ -361,7 +359,7 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     c->batch = batch;
     c->n = n;
     c->stream = (hipStream_t)stream;
-    const int k = p[0].fp16_exp ? p[0].fp16_exp : 16;
+    const int k = p[0].fp16_exp ? p[0].fp16_exp : 14;
     c->scale = std::ldexp(1.0f, k);
     c->iscale = std::ldexp(1.0f, -k);
     layout(p, n, c->b, &c->inst, &c->elems, &c->nodes);

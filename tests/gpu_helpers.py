@@ -4,7 +4,7 @@ import numpy as np
 
 from oracle import oracle as O
 
-COLL_ORC = {"minxent4": O.MINXENT4, "minxent2": O.MINXENT2, "srt": O.SRT}
+COLL_ORC = {"minxent4": O.MINXENT4, "minxent2": O.MINXENT2, "srt": O.SRT, "trt": O.TRT, "mrt": O.MRT}
 BC_ORC = {"periodic": O.BC_PERIODIC, "tube": O.BC_TUBE, "cavity": O.BC_CAVITY, "box": O.BC_BOX}
 
 
@@ -39,7 +39,7 @@ def gpu_run(lattice, collision, bc, precision, nx, ny, tau, rho, ux, uy=None, st
 def orc_run(lattice, collision, bc, nx, ny, tau, rho, ux, uy=None, steps=1, u_lid=0.0, rho0=1.0, tau2=0.0,
             window=None):
     lat = O.D1Q3 if lattice == "d1q3" else O.D2Q9
-    if collision == "minxent2" and tau2 <= 0.0:
+    if collision in ("minxent2", "trt", "mrt") and tau2 <= 0.0:
         tau2 = (8 * tau - 1) / (2 * tau - 1)
     return O.run(lat, COLL_ORC[collision], BC_ORC[bc], nx, ny, tau, rho, ux, uy, steps=steps, tau2=tau2,
                  u_lid=u_lid, rho0=rho0, window=window)

@@ -48,11 +48,14 @@ def test_d1q3_sizes_and_boundaries(nx, bc, steps):
 # D2Q9, every collision rule and boundary kind, ragged sizes
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("collision", ["minxent4", "minxent2", "srt"])
+COLLISIONS = ["minxent4", "minxent2", "srt", "trt", "mrt"]
+
+
+@pytest.mark.parametrize("collision", COLLISIONS)
 @pytest.mark.parametrize("bc", ["cavity", "periodic", "tube", "box"])
 def test_d2q9_small_fp64(collision, bc):
     nx, ny, steps, tau = 45, 37, 30, 0.57
-    seed = 10 * ["minxent4", "minxent2", "srt"].index(collision) + ["cavity", "periodic", "tube", "box"].index(bc)
+    seed = 10 * COLLISIONS.index(collision) + ["cavity", "periodic", "tube", "box"].index(bc)
     rho, ux, uy = smooth_fields(nx, ny, seed=seed)
     g = gpu_run("d2q9", collision, bc, "fp64", nx, ny, tau, rho, ux, uy, steps=steps, u_lid=0.08)
     o = orc_run("d2q9", collision, bc, nx, ny, tau, rho, ux, uy, steps=steps, u_lid=0.08)
