@@ -90,6 +90,128 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
             "fields": {"rho": r, "ux": u, "uy": v}, "status": st}
 
 
+def time_batch(B, torch, params, rho, ux, uy, steps, warmup):
+    """Time a batched context (one launch per step over every instance)."""
+    ws = torch.empty(B.lbm_workspace_bytes_batch(params), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    ctx = B.lbm_init_batch(params, rho, ux, uy, workspace=ws, stream=stream)
+    variant = B.lbm_autotune(ctx)
+    B.lbm_step(ctx, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    B.lbm_step(ctx, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = B.lbm_info(ctx)
+    r, u, v = B.lbm_moments(ctx)
+    st = B.lbm_status(ctx)
+    per = B.lbm_status_batch(ctx, len(params))
+    shape = B.lbm_variant_name(ctx, variant)
+    B.lbm_free(ctx)
+    del ws
+    return {"wall_s": wall, "event_ms": e0.elapsed_time(e1), "variant": shape, "nodes": info["nodes"],
+            "bytes_per_step": info["bytes_per_step"], "fields": {"rho": r, "ux": u, "uy": v}, "status": st,
+            "per_instance": per}
+
+
+def rate(res, steps):
+    mlups = res["nodes"] * steps / res["wall_s"] / 1e6
+    gbs = res["bytes_per_step"] / (res["event_ms"] / steps * 1e-3) / 1e9
+    return {"mlups": round(mlups, 1), "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "launch_shape": res["variant"], "unstable": res["status"]["unstable"]}
+
+
+def rel_errors(a, b, mask):
+    import numpy as np
+    out = {}
+    for k in ("rho", "ux", "uy"):
+        x, y = a[k][mask], b[k][mask]
+        if not np.any(y):
+            continue
+        d = x - y
+        out[k] = {"max_rel": float(np.max(np.abs(d)) / np.max(np.abs(y))),
+                  "l2_rel": float(np.sqrt(np.sum(d * d) / np.sum(y * y)))}
+    return out
+
+
+def batched_cavities(B, torch, I, steps, warmup):
+    """512 cavities, sides log-uniform in [32, 512], Re uniform in [100, 1e4],
+    lid 0.1, FP32, one launch per step; error against the same batch in FP64."""
+    import numpy as np
+    insts = I.cavity_batch(count=512)
+    fields = [I.cavity_fields(n, 1.0, 1804 * 1000 + i) for i, (n, tau, re) in enumerate(insts)]
+    rho = np.concatenate([f[0].ravel() for f in fields])
+    ux = np.zeros_like(rho)
+    masks = []
+    for n, tau, re in insts:
+        m = np.zeros((n, n), bool)
+        m[1:-1, 1:-1] = True
+        masks.append(m.ravel())
+    mask = np.concatenate(masks)
+    out = {}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        params = [B.make_params("d2q9", "minxent4", "cavity", prec, n, n, tau, 0.0, 0.1, 1.0) for n, tau, re in insts]
+        res[prec] = time_batch(B, torch, params, rho, ux, ux, steps, warmup)
+        out[prec] = rate(res[prec], steps)
+    out["field_error_fp32_vs_fp64"] = rel_errors(res["fp32"]["fields"], res["fp64"]["fields"], mask)
+    out["instances"] = len(insts)
+    out["nodes"] = res["fp32"]["nodes"]
+    out["timed_steps"] = steps
+    return out
+
+
+def fp16_cavity(B, torch, I, steps, warmup, tune_cache):
+    """8192^2 cavity, lid 0.05, Re 5000: FP16 deviation storage against FP64."""
+    import numpy as np
+    c = I.cavity_8192_params()
+    n = c["nx"]
+    fields = I.cavity_fields(n, 1.0, c["seed"])
+    out, res = {}, {}
+    for prec in ("fp16dev", "fp64"):
+        res[prec] = time_form(B, torch, prec, n, c["tau"], c["u_lid"], fields, steps, warmup, tune_cache)
+        out[prec] = rate(res[prec], steps)
+    m = np.zeros((n, n), bool)
+    m[1:-1, 1:-1] = True
+    out["field_error_fp16dev_vs_fp64"] = rel_errors(res["fp16dev"]["fields"], res["fp64"]["fields"], m.ravel())
+    out["nodes"] = n * n
+    out["timed_steps"] = steps
+    return out
+
+
+def fp16_tubes(B, torch, I, steps, warmup):
+    """4096 D1Q3 shock tubes, lengths log-uniform in [1024, 65536], density
+    ratio in [1.5, 4], tau in [0.505, 0.6]: FP16 deviations against FP64.
+    On D1Q3 the method is SRT, which breaks down for the sharpest tubes near
+    tau = 1/2; errors are taken over the instances stable in both forms and
+    the unstable ones are counted."""
+    import numpy as np
+    tubes = I.tube_batch(count=4096)
+    rho = np.concatenate([I.tube_fields(n, rl, rr)[0] for n, rl, rr, tau in tubes])
+    ux = np.zeros_like(rho)
+    out, res = {}, {}
+    for prec in ("fp16dev", "fp64"):
+        params = [B.make_params("d1q3", "srt", "tube", prec, n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr))
+                  for n, rl, rr, tau in tubes]
+        res[prec] = time_batch(B, torch, params, rho, ux, None, steps, warmup)
+        out[prec] = rate(res[prec], steps)
+        out[prec]["unstable_instances"] = int(sum(s_["unstable"] for s_ in res[prec]["per_instance"]))
+    masks = []
+    for k, (n, rl, rr, tau) in enumerate(tubes):
+        ok = not (res["fp16dev"]["per_instance"][k]["unstable"] or res["fp64"]["per_instance"][k]["unstable"])
+        masks.append(np.r_[False, np.full(n - 2, ok), False])
+    out["field_error_fp16dev_vs_fp64_stable_instances"] = rel_errors(res["fp16dev"]["fields"],
+                                                                     res["fp64"]["fields"], np.concatenate(masks))
+    out["instances"] = len(tubes)
+    out["nodes"] = res["fp16dev"]["nodes"]
+    out["timed_steps"] = steps
+    return out
+
+
 def copy_bandwidth(B, torch, nbytes=2 << 30, reps=10):
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -137,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and FP16 workloads")
+    ap.add_argument("--extra-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernel; "
@@ -193,6 +317,14 @@ def main():
                        "achieved_gbs": round(ref["bytes_per_step"] / (ref["event_ms"] / args.steps * 1e-3) / 1e9, 1),
                        "speedup_of_headline": round(value / fp64_mlups, 3)}
         out["field_error_vs_fp64"] = fluid_errors(head["fields"], ref["fields"], n)
+    if not args.no_extra:
+        ref32 = time_form(B, torch, "fp32", n, tau, cfg["u_lid"], fields, args.extra_steps, args.warmup,
+                          args.tune_cache)
+        out["fp32"] = rate(ref32, args.extra_steps)
+        out["batched_cavities_512"] = batched_cavities(B, torch, I, args.extra_steps, args.warmup)
+        out["fp16dev_cavity_8192"] = fp16_cavity(B, torch, I, min(args.extra_steps, 300), args.warmup,
+                                                 args.tune_cache)
+        out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup)
     out["copy_kernel_gbs"] = round(copy_bandwidth(B, torch), 1)
     out["kernel_source_sha256_16"] = digest
     if not args.no_cpu_baseline:

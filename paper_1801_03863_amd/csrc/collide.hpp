@@ -89,9 +89,39 @@ __device__ __forceinline__ void batch_rcp(const double (&x)[N], double (&r)[N], 
 // s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd series through s^19
 // (truncation below 2^-54), and k ln 2 added with ln 2 split into a 32-bit
 // head and a tail (the Cody-Waite / fdlibm split).  The four divisions share
-// one reciprocal.  Error <= 2-3 ulp.
+// one reciprocal.  Error <= 2-3 ulp on both paths.
 __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
 {
+    // Fast path, taken when every argument is within 1/16 of one (always the
+    // case near equilibrium): t = y - 1 is exact, s = t/(2 + t) has
+    // |s| <= 0.0323 and the series through s^11 is below 2^-60.
+    double t[4];
+    bool near = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        t[i] = y[i] - 1.0;
+        near = near && __builtin_fabs(t[i]) < 0.0625;
+    }
+    if (near) {
+        double den[4], rd[4], prod;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) den[i] = 2.0 + t[i];
+        batch_rcp<4>(den, rd, prod);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double s = t[i] * rd[i];
+            const double z = s * s;
+            double p = 1.0 / 13.0;
+            p = __builtin_fma(p, z, 1.0 / 11.0);
+            p = __builtin_fma(p, z, 1.0 / 9.0);
+            p = __builtin_fma(p, z, 1.0 / 7.0);
+            p = __builtin_fma(p, z, 1.0 / 5.0);
+            p = __builtin_fma(p, z, 1.0 / 3.0);
+            const double tt = s + s;
+            out[i] = __builtin_fma(tt * z, p, tt);
+        }
+        return;
+    }
     double m[4], den[4], rd[4], kd[4], prod;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -117,8 +147,8 @@ __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
         p = __builtin_fma(p, z, 1.0 / 7.0);
         p = __builtin_fma(p, z, 1.0 / 5.0);
         p = __builtin_fma(p, z, 1.0 / 3.0);
-        const double t = s + s;
-        const double lnm = __builtin_fma(t * z, p, t);
+        const double tt = s + s;
+        const double lnm = __builtin_fma(tt * z, p, tt);
         out[i] = __builtin_fma(kd[i], 6.93147180369123816490e-01,
                                __builtin_fma(kd[i], 1.90821492927058770002e-10, lnm));
     }
@@ -251,12 +281,13 @@ __device__ __forceinline__ void collide_mrt(C (&f)[9], C be, C bp, C bq, C bs)
 }
 
 // MinxEnt collision with a single Newton step.  MX2 selects MinxEnt2 (only
-// e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).
-// Returns true
-// if the node was guarded: its start point had a population <= 0 or not
+// e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).  Returns true if
+// the node was guarded: its start point had a population <= 0 or not
 // finite, in which case f holds the start point itself (no Newton step).
+// `finite` is false if the result has an inf or NaN (the start point is
+// finite, so only the Newton increments can make it so).
 template <class C, bool MX2>
-__device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
+__device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bool &finite)
 {
     // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C).
     const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -279,36 +310,23 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
         q5 = k2 * (m5 + jx) * C(1.0 / 12.0);
         q7 = k2 * (m7 + jy) * C(1.0 / 12.0);
     }
-    // Start point: equilibrium part e_a (deviation from W_a rho) and the
+    // Start point: the polynomial equilibrium W_a rho (1 + e_a) plus the
     // non-equilibrium corrections c_a.
-    const C b = -C(1.5) * (ux * ux + uy * uy);
+    const C b1 = C(1) - C(1.5) * (ux * ux + uy * uy);
     const C s = ux + uy, d = ux - uy;
-    C e[9], c[9];
-    e[0] = b;
-    e[1] = C(4.5) * ux * ux + b + C(3) * ux;
-    e[2] = C(4.5) * uy * uy + b + C(3) * uy;
-    e[3] = C(4.5) * ux * ux + b - C(3) * ux;
-    e[4] = C(4.5) * uy * uy + b - C(3) * uy;
-    e[5] = C(4.5) * s * s + b + C(3) * s;
-    e[6] = C(4.5) * d * d + b - C(3) * d;
-    e[7] = C(4.5) * s * s + b - C(3) * s;
-    e[8] = C(4.5) * d * d + b + C(3) * d;
-    c[0] = C(0);
-    c[1] = q8 - C(2) * q5;
-    c[2] = -q8 - C(2) * q7;
-    c[3] = q8 + C(2) * q5;
-    c[4] = -q8 + C(2) * q7;
-    c[5] = q9 + q5 + q7;
-    c[6] = -q9 - q5 + q7;
-    c[7] = q9 - q5 - q7;
-    c[8] = -q9 + q5 - q7;
+    const C hx = C(4.5) * ux * ux + b1, hy = C(4.5) * uy * uy + b1;
+    const C hs = C(4.5) * s * s + b1, hd = C(4.5) * d * d + b1;
     const C wr = W9<C>::rest * rho, wa = W9<C>::axis * rho, wd = W9<C>::diag * rho;
     C f0[9];
-    f0[0] = wr + wr * e[0];
-#pragma unroll
-    for (int a = 1; a < 5; ++a) f0[a] = (wa + wa * e[a]) + c[a];
-#pragma unroll
-    for (int a = 5; a < 9; ++a) f0[a] = (wd + wd * e[a]) + c[a];
+    f0[0] = wr * b1;
+    f0[1] = wa * (hx + C(3) * ux) + (q8 - C(2) * q5);
+    f0[2] = wa * (hy + C(3) * uy) - (q8 + C(2) * q7);
+    f0[3] = wa * (hx - C(3) * ux) + (q8 + C(2) * q5);
+    f0[4] = wa * (hy - C(3) * uy) - (q8 - C(2) * q7);
+    f0[5] = wd * (hs + C(3) * s) + (q9 + (q5 + q7));
+    f0[6] = wd * (hd - C(3) * d) - (q9 + (q5 - q7));
+    f0[7] = wd * (hs - C(3) * s) + (q9 - (q5 + q7));
+    f0[8] = wd * (hd + C(3) * d) - (q9 - (q5 - q7));
 
     // Guard: every start population positive and finite.  The minimum
     // catches values <= 0; the product (double) or sum (float) is not finite
@@ -333,6 +351,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
     if (!ok) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) f[a] = f0[a];
+        C sm = f0[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) sm += f0[a];
+        finite = __builtin_fabs(sm) < C(__builtin_huge_valf());  // inf and NaN fail
         return true;
     }
 
@@ -388,6 +410,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2)
         dy = g[3];
     }
 
+    finite = __builtin_fabs((de + dp) + (dx + dy)) < C(__builtin_huge_valf());
     // f_post = f0 - A delta.
     const C axis = de + C(2) * dp;
     const C dgn = C(2) * de + dp;

@@ -160,27 +160,34 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
         t = f[6]; f[6] = f[8]; f[8] = t;
         return 0;
     }
-    int flags = 0;
-    if constexpr (CO == CO_SRT) {
-        collide_srt<C>(f, C(in.omega));
-    } else if constexpr (CO == CO_TRT) {
-        collide_mrt<C>(f, C(in.omega), C(in.omega), C(in.omega2), C(in.omega));
-    } else if constexpr (CO == CO_MRT) {
-        collide_mrt<C>(f, C(1.64), C(1.54), C(in.omega2), C(in.omega));
-    } else {
-        const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2));
-        flags |= g ? 2 : 0;
-    }
-    // Stable iff every population is >= 0 and finite: the minimum catches
-    // negatives, the sum catches inf and NaN.
-    C mn = f[0], sm = f[0];
+    // Stable iff every population is >= 0 and finite (Sec. IV.G): the
+    // minimum catches negatives; inf and NaN are caught by the Newton
+    // increments (MinxEnt) or by the sum (the other rules).
+    if constexpr (CO == CO_MINXENT4 || CO == CO_MINXENT2) {
+        bool fin = true;
+        const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2), fin);
+        C mn = f[0];
 #pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        mn = __builtin_fmin(mn, f[a]);
-        sm += f[a];
+        for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f[a]);
+        const bool ok = fin && mn >= C(0);
+        return (g ? 2 : 0) | (ok ? 0 : 1);
+    } else {
+        if constexpr (CO == CO_SRT) {
+            collide_srt<C>(f, C(in.omega));
+        } else if constexpr (CO == CO_TRT) {
+            collide_mrt<C>(f, C(in.omega), C(in.omega), C(in.omega2), C(in.omega));
+        } else {
+            collide_mrt<C>(f, C(1.64), C(1.54), C(in.omega2), C(in.omega));
+        }
+        C mn = f[0], sm = f[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            mn = __builtin_fmin(mn, f[a]);
+            sm += f[a];
+        }
+        const bool ok = mn >= C(0) && sm < C(__builtin_huge_valf());
+        return ok ? 0 : 1;
     }
-    const bool ok = mn >= C(0) && sm < C(__builtin_huge_valf());
-    return flags | (ok ? 0 : 1);
 }
 
 // Wave-level status update: one atomic per wave and kind.
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restr
     report(a.status, bad, 0, a.step, a.step_base);
 }
 
-template <int ST, int BLK>
+template <int ST, int BLK, int NPT>
 __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *__restrict__ src,
                                                     typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
@@ -364,11 +371,16 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *
     const int i = a.tile_inst[t];
     const Inst &in = a.inst[i];
     const int nx = in.nx;
-    const int x = a.tile_first[t] + (int)threadIdx.x;
-    const bool valid = x < nx;
-    const int fl = step3_node<ST>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
-                                  C(in.omega), C(in.rho0), a, valid);
-    report(a.status + i, valid && fl, 0, a.step, a.step_base);
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int x = a.tile_first[t] + k * BLK + (int)threadIdx.x;
+        const bool valid = x < nx;
+        const int fl = step3_node<ST>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
+                                      C(in.omega), C(in.rho0), a, valid);
+        bad = bad || (valid && fl);
+    }
+    report(a.status + i, bad, 0, a.step, a.step_base);
 }
 
 // --------------------------------------------------------------------------
@@ -625,14 +637,27 @@ hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipSt
     }
 }
 
+// Batched launch shapes: D2Q9 tiles of 256 or 128 nodes (one per thread);
+// D1Q3 tiles of BLK x NPT nodes.
+struct ShapeB {
+    int blk, npt;
+    const char *name;
+};
+constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"}};
+constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
+                                {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"}};
+
 template <int ST>
 hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
     using T = typename Form<ST>::T;
-    if (v == 0)
-        hipLaunchKernelGGL((k_d1q3_batch<ST, 256>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a);
-    else
-        hipLaunchKernelGGL((k_d1q3_batch<ST, 128>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 1>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 1: hipLaunchKernelGGL((k_d1q3_batch<ST, 128, 1>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
+    case 2: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 4>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 3: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 8>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -670,7 +695,17 @@ int d2q9_variant_count(int coll) { return coll == CO_MINXENT4 ? kNumShapes : kNu
 const char *d2q9_variant_name(int v) { return (v >= 0 && v < kNumShapes) ? kShapes[v].name : "?"; }
 int d1q3_variant_count() { return kNumShapes3; }
 const char *d1q3_variant_name(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].name : "?"; }
-int batch_variant_count() { return 2; }
+int batch_variant_count(int lattice) { return lattice == 3 ? 4 : 2; }
+int batch_tile_nodes(int lattice, int v)
+{
+    if (lattice == 3) return (v >= 0 && v < 4) ? kShapesB3[v].blk * kShapesB3[v].npt : 0;
+    return (v >= 0 && v < 2) ? kShapesB9[v].blk * kShapesB9[v].npt : 0;
+}
+const char *batch_variant_name(int lattice, int v)
+{
+    if (lattice == 3) return (v >= 0 && v < 4) ? kShapesB3[v].name : "?";
+    return (v >= 0 && v < 2) ? kShapesB9[v].name : "?";
+}
 
 hipError_t launch_d2q9_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
@@ -687,7 +722,7 @@ hipError_t launch_d2q9_step(int st, int coll, int v, const void *src, void *dst,
 hipError_t launch_d2q9_batch_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a,
                                   hipStream_t s)
 {
-    if (v < 0 || v >= batch_variant_count()) return hipErrorInvalidValue;
+    if (v < 0 || v >= batch_variant_count(9)) return hipErrorInvalidValue;
     switch (st) {
     case ST_F64: return dispatch9bc<ST_F64>(coll, v, src, dst, a, s);
     case ST_F32N64: return dispatch9bc<ST_F32N64>(coll, v, src, dst, a, s);
@@ -710,7 +745,7 @@ hipError_t launch_d1q3_step(int st, int v, const void *src, void *dst, const Ste
 
 hipError_t launch_d1q3_batch_step(int st, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
-    if (v < 0 || v >= batch_variant_count()) return hipErrorInvalidValue;
+    if (v < 0 || v >= batch_variant_count(3)) return hipErrorInvalidValue;
     switch (st) {
     case ST_F64: return dispatch3b<ST_F64>(v, src, dst, a, s);
     case ST_F32N64: return dispatch3b<ST_F32N64>(v, src, dst, a, s);

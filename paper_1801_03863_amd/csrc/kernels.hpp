@@ -63,7 +63,9 @@ hipError_t launch_d1q3_step(int storage, int variant, const void *src, void *dst
                             hipStream_t s);
 hipError_t launch_d1q3_batch_step(int storage, int variant, const void *src, void *dst,
                                   const StepArgs &a, hipStream_t s);
-int batch_variant_count();
+int batch_variant_count(int lattice);
+int batch_tile_nodes(int lattice, int variant);
+const char *batch_variant_name(int lattice, int variant);
 
 // Set the state of one instance: pre-shifted equilibrium of FP64 fields
 // (d_rho, d_ux, d_uy: nx*ny device doubles) or of FP64 populations (d_f:

@@ -203,7 +203,6 @@ int build_tiles(lbm_ctx *c, int tile_nodes)
     return LBM_OK;
 }
 
-int batch_tile_nodes(int variant) { return variant == 0 ? 256 : 128; }
 
 void drop_graphs(lbm_ctx *c)
 {
@@ -245,7 +244,7 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
 
 int variant_count(const lbm_ctx *c)
 {
-    if (c->batch) return lbm::batch_variant_count();
+    if (c->batch) return lbm::batch_variant_count(c->b);
     return c->b == 9 ? lbm::d2q9_variant_count(c->p.collision) : lbm::d1q3_variant_count();
 }
 
@@ -406,7 +405,7 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     if (batch) {
         CK(hipMalloc(&c->d_inst, sizeof(Inst) * n));
         CK(hipMemcpy(c->d_inst, c->inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice));
-        rc = build_tiles(c, batch_tile_nodes(0));
+        rc = build_tiles(c, lbm::batch_tile_nodes(c->b, 0));
         if (rc) {
             destroy(c);
             return rc;
@@ -515,7 +514,7 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
     else HIPCHK(hipDeviceSynchronize());
     drop_graphs(c);
     c->variant = v;
-    if (c->batch && batch_tile_nodes(v) != c->tile_nodes) return build_tiles(c, batch_tile_nodes(v));
+    if (c->batch && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes) return build_tiles(c, lbm::batch_tile_nodes(c->b, v));
     return LBM_OK;
 }
 
@@ -524,7 +523,7 @@ int lbm_variant_count(const lbm_ctx_t *c) { return c ? variant_count(c) : 0; }
 const char *lbm_variant_name(const lbm_ctx_t *c, int32_t v)
 {
     if (!c) return "?";
-    if (c->batch) return v == 0 ? "batch 256 nodes/block" : (v == 1 ? "batch 128 nodes/block" : "?");
+    if (c->batch) return lbm::batch_variant_name(c->b, v);
     return c->b == 9 ? lbm::d2q9_variant_name(v) : lbm::d1q3_variant_name(v);
 }
 
@@ -563,21 +562,25 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
         int rc = lbm_set_variant(c, v);
         if (rc) return rc;
         // Source buffer is the current state and is never written here.
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < 3; ++r) {
             lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
             HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
         }
-        HIPCHK(hipEventRecord(e0, c->stream));
-        for (int r = 0; r < reps; ++r) {
-            lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
-            HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+        float shape_best = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            HIPCHK(hipEventRecord(e0, c->stream));
+            for (int r = 0; r < reps; ++r) {
+                lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
+                HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+            }
+            HIPCHK(hipEventRecord(e1, c->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            shape_best = std::min(shape_best, ms);
         }
-        HIPCHK(hipEventRecord(e1, c->stream));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
+        if (shape_best < best) {
+            best = shape_best;
             best_v = v;
         }
     }

@@ -246,3 +246,27 @@ def test_reduced_precision_forms_long_run_error():
                        (np.sum(ref[1] ** 2) + np.sum(ref[2] ** 2)))
         print(prec, "rho max %.2e  u max %.2e  u L2 %.2e" % (e_rho, e_u, l2_u), flush=True)
         assert e_rho <= tol_rho and e_u <= tol_u, prec
+
+
+def test_batched_tube_shapes_bitwise():
+    tubes = I.tube_batch(count=4096)[:40]
+    b = B()
+    params = [b.make_params("d1q3", "srt", "tube", "fp16dev", n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr))
+              for n, rl, rr, tau in tubes]
+    rho = np.concatenate([I.tube_fields(n, rl, rr)[0] for n, rl, rr, tau in tubes])
+    ux = np.zeros_like(rho)
+    ref = None
+    ctx = b.lbm_init_batch(params, rho, ux, None)
+    nv = b.lbm_variant_count(ctx)
+    b.lbm_free(ctx)
+    assert nv == 4
+    for v in range(nv):
+        ctx = b.lbm_init_batch(params, rho, ux, None)
+        try:
+            b.lbm_set_variant(ctx, v)
+            b.lbm_step(ctx, 30)
+            F = b.lbm_get_populations(ctx, 3)
+        finally:
+            b.lbm_free(ctx)
+        ref = F if ref is None else ref
+        assert np.array_equal(ref, F), v
