@@ -44,13 +44,25 @@ __device__ __forceinline__ typename Form<ST>::C load(const typename Form<ST>::T 
     else return C(*p);
 }
 
-template <int ST>
+// Raw load of one stored population; NT marks it non-temporal (streamed:
+// every population is read once per step).
+template <class T, bool NT>
+__device__ __forceinline__ T ldraw(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <int ST, bool NT = false>
 __device__ __forceinline__ void store(typename Form<ST>::T *p, typename Form<ST>::C v, typename Form<ST>::C ref,
                                       float scale)
 {
     using T = typename Form<ST>::T;
-    if constexpr (ST == ST_F16DEV) *p = T((v - ref) * scale);
-    else *p = T(v);
+    T t;
+    if constexpr (ST == ST_F16DEV) t = T((v - ref) * scale);
+    else t = T(v);
+    if constexpr (NT) __builtin_nontemporal_store(t, p);
+    else *p = t;
 }
 
 template <class C>
@@ -106,7 +118,7 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
 // uniform (scalar registers); per-lane addressing is one 32-bit byte offset
 // per row/column combination, so loads use the scalar-base + vector-offset
 // form.
-template <int ST>
+template <int ST, bool NT = false>
 __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
                                       const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
                                       typename Form<ST>::C (&f)[9])
@@ -117,19 +129,22 @@ __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s
     const uint32_t E = sizeof(T);
     const uint32_t rc = (uint32_t)(y * nx) * E, rm = (uint32_t)(n.ym * nx) * E, rp = (uint32_t)(n.yp * nx) * E;
     const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
-    f[0] = load<ST>((const T *)(b + (rc + cc)), ref[0], iscale);
-    f[1] = load<ST>((const T *)(b + PB + (rc + cm)), ref[1], iscale);
-    f[2] = load<ST>((const T *)(b + 2 * PB + (rm + cc)), ref[2], iscale);
-    f[3] = load<ST>((const T *)(b + 3 * PB + (rc + cp)), ref[3], iscale);
-    f[4] = load<ST>((const T *)(b + 4 * PB + (rp + cc)), ref[4], iscale);
-    f[5] = load<ST>((const T *)(b + 5 * PB + (rm + cm)), ref[5], iscale);
-    f[6] = load<ST>((const T *)(b + 6 * PB + (rm + cp)), ref[6], iscale);
-    f[7] = load<ST>((const T *)(b + 7 * PB + (rp + cp)), ref[7], iscale);
-    f[8] = load<ST>((const T *)(b + 8 * PB + (rp + cm)), ref[8], iscale);
+    T r[9];
+    r[0] = ldraw<T, NT>((const T *)(b + (rc + cc)));
+    r[1] = ldraw<T, NT>((const T *)(b + PB + (rc + cm)));
+    r[2] = ldraw<T, NT>((const T *)(b + 2 * PB + (rm + cc)));
+    r[3] = ldraw<T, NT>((const T *)(b + 3 * PB + (rc + cp)));
+    r[4] = ldraw<T, NT>((const T *)(b + 4 * PB + (rp + cc)));
+    r[5] = ldraw<T, NT>((const T *)(b + 5 * PB + (rm + cm)));
+    r[6] = ldraw<T, NT>((const T *)(b + 6 * PB + (rm + cp)));
+    r[7] = ldraw<T, NT>((const T *)(b + 7 * PB + (rp + cp)));
+    r[8] = ldraw<T, NT>((const T *)(b + 8 * PB + (rp + cm)));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = load<ST>(&r[q], ref[q], iscale);
 }
 
 // Write the nine post-collision populations of node index i.
-template <int ST>
+template <int ST, bool NT = false>
 __device__ __forceinline__ void push9(typename Form<ST>::T *__restrict__ d, int64_t P, int i,
                                       const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
                                       float scale)
@@ -139,7 +154,7 @@ __device__ __forceinline__ void push9(typename Form<ST>::T *__restrict__ d, int6
     const int64_t PB = P * (int64_t)sizeof(T);
     const uint32_t o = (uint32_t)i * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) store<ST>((T *)(b + q * PB + o), f[q], ref[q], scale);
+    for (int q = 0; q < 9; ++q) store<ST, NT>((T *)(b + q * PB + o), f[q], ref[q], scale);
 }
 
 // Role collision of one D2Q9 node.  Returns bit 0 = unstable, bit 1 = guarded.
@@ -221,7 +236,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // never spans two rows); it covers BX columns and BY*RPT rows.
 // --------------------------------------------------------------------------
 
-template <int ST, int CO, int BX, int BY, int RPT>
+template <int ST, int CO, int BX, int BY, int RPT, int NT = 0>
 __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__restrict__ src,
                                                  typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
@@ -245,12 +260,77 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
         if (y >= ny) break;  // wave-uniform: a wave lies in one row
         const Nb n = neighbours(xs, y, nx, ny, a.bc);
         C f[9];
-        pull9<ST>(src, P, xs, y, nx, n, ref, a.fp16_iscale, f);
+        pull9<ST, (NT & 1) != 0>(src, P, xs, y, nx, n, ref, a.fp16_iscale, f);
         const int role = role9(xs, y, nx, ny, a.bc);
         const int fl = node9<ST, CO>(f, role, in);
         bad = bad || (xin && (fl & 1));
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9<ST>(dst, P, y * nx + x, f, ref, a.fp16_scale);
+        if (xin) push9<ST, (NT & 2) != 0>(dst, P, y * nx + x, f, ref, a.fp16_scale);
+    }
+    report(a.status, bad, guarded, a.step, a.step_base);
+}
+
+// Software-pipelined form: a block of BX threads walks RPT consecutive rows;
+// each thread issues the raw loads of its next row before computing the
+// current one, so nine loads per thread are always in flight while the VALU
+// works.  Same per-node arithmetic as k_d2q9 (bitwise identical results).
+template <int ST, bool NT = false>
+__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
+                                          const Nb &n, typename Form<ST>::T (&r)[9])
+{
+    using T = typename Form<ST>::T;
+    const char *b = (const char *)s;
+    const int64_t PB = P * (int64_t)sizeof(T);
+    const uint32_t E = sizeof(T);
+    const uint32_t rc = (uint32_t)(y * nx) * E, rm = (uint32_t)(n.ym * nx) * E, rp = (uint32_t)(n.yp * nx) * E;
+    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
+    r[0] = ldraw<T, NT>((const T *)(b + (rc + cc)));
+    r[1] = ldraw<T, NT>((const T *)(b + PB + (rc + cm)));
+    r[2] = ldraw<T, NT>((const T *)(b + 2 * PB + (rm + cc)));
+    r[3] = ldraw<T, NT>((const T *)(b + 3 * PB + (rc + cp)));
+    r[4] = ldraw<T, NT>((const T *)(b + 4 * PB + (rp + cc)));
+    r[5] = ldraw<T, NT>((const T *)(b + 5 * PB + (rm + cm)));
+    r[6] = ldraw<T, NT>((const T *)(b + 6 * PB + (rm + cp)));
+    r[7] = ldraw<T, NT>((const T *)(b + 7 * PB + (rp + cp)));
+    r[8] = ldraw<T, NT>((const T *)(b + 8 * PB + (rp + cm)));
+}
+
+template <int ST, int CO, int BX, int RPT, int NT = 0>
+__global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__restrict__ src,
+                                                typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    const Inst &in = a.one;
+    const int nx = in.nx, ny = in.ny;
+    const int64_t P = in.plane;
+    int b = blockIdx.x;
+    if (a.xcd_swizzle) b = xcd_remap(b, gridDim.x);
+    const int tx = b % a.tiles_x, ty = b / a.tiles_x;
+    const int x = tx * BX + (int)threadIdx.x;
+    const bool xin = x < nx;
+    const int xs = xin ? x : nx - 1;
+    const int y0 = ty * RPT;
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+    bool bad = false;
+    int guarded = 0;
+    T raw[9];
+    pull9_raw<ST, (NT & 1) != 0>(src, P, xs, y0, nx, neighbours(xs, y0, nx, ny, a.bc), raw);
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = y0 + k;
+        if (y >= ny) break;  // uniform across the block
+        C f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
+        if (k + 1 < RPT && y + 1 < ny)
+            pull9_raw<ST, (NT & 1) != 0>(src, P, xs, y + 1, nx, neighbours(xs, y + 1, nx, ny, a.bc), raw);
+        const int role = role9(xs, y, nx, ny, a.bc);
+        const int fl = node9<ST, CO>(f, role, in);
+        bad = bad || (xin && (fl & 1));
+        guarded += __popcll(__ballot(xin && (fl & 2)));
+        if (xin) push9<ST, (NT & 2) != 0>(dst, P, y * nx + x, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -260,7 +340,7 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
 // one instance; tile tables give its instance and first node.
 // --------------------------------------------------------------------------
 
-template <int ST, int CO, int BLK>
+template <int ST, int CO, int BLK, int NT = 0>
 __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *__restrict__ src,
                                                     typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
@@ -285,12 +365,83 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     const Nb n = neighbours(x, y, nx, ny, a.bc);
     const typename Form<ST>::T *s = src + in.offset;
     C f[9];
-    pull9<ST>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
+    pull9<ST, (NT & 1) != 0>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
     const int role = role9(x, y, nx, ny, a.bc);
     const int fl = node9<ST, CO>(f, role, in);
-    if (valid) push9<ST>(dst + in.offset, P, node, f, ref, a.fp16_scale);
+    if (valid) push9<ST, (NT & 2) != 0>(dst + in.offset, P, node, f, ref, a.fp16_scale);
     const int guarded = __popcll(__ballot(valid && (fl & 2)));
     report(a.status + i, valid && (fl & 1), guarded, a.step, a.step_base);
+}
+
+// --------------------------------------------------------------------------
+// D2Q9, batch of small lattices resident in LDS: one workgroup per instance
+// runs `nsteps` steps inside one launch.  Both population buffers live in
+// LDS at storage precision (so every step rounds exactly as the per-step
+// kernels do and results are bitwise identical); a workgroup barrier
+// separates the steps.  The state is read from `src` once and the final
+// state written to `dst` once (they may be the same buffer: every read
+// happens before the first write).
+// --------------------------------------------------------------------------
+
+template <int ST, int CO>
+__global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *src, typename Form<ST>::T *dst,
+                                                   StepArgs a, int nsteps)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int i = blockIdx.x;
+    const Inst &in = a.inst[i];
+    const int nx = in.nx, ny = in.ny;
+    const int nodes = nx * ny;
+    T *L0 = (T *)lds_raw;
+    T *L1 = L0 + 9 * nodes;
+    const T *g = src + in.offset;
+    for (int idx = threadIdx.x; idx < 9 * nodes; idx += blockDim.x) {
+        const int q = idx / nodes, j = idx - q * nodes;
+        L0[idx] = g[q * in.plane + j];
+    }
+    __syncthreads();
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+    const float inx = __builtin_amdgcn_rcpf((float)nx);
+    int64_t first_bad = INT64_MAX;
+    int64_t guarded = 0;
+    for (int k = 0; k < nsteps; ++k) {
+        const T *sin = (k & 1) ? L1 : L0;
+        T *sout = (k & 1) ? L0 : L1;
+        for (int node = threadIdx.x; node < nodes; node += blockDim.x) {
+            int y = (int)((float)node * inx);
+            int x = node - y * nx;
+            if (x < 0) { --y; x += nx; }
+            if (x >= nx) { ++y; x -= nx; }
+            const Nb n = neighbours(x, y, nx, ny, a.bc);
+            C f[9];
+            pull9<ST>(sin, nodes, x, y, nx, n, ref, a.fp16_iscale, f);
+            const int fl = node9<ST, CO>(f, role9(x, y, nx, ny, a.bc), in);
+            if ((fl & 1) && first_bad == INT64_MAX) first_bad = k;
+            guarded += (fl >> 1) & 1;
+            push9<ST>(sout, nodes, node, f, ref, a.fp16_scale);
+        }
+        __syncthreads();
+    }
+    const T *fin = (nsteps & 1) ? L1 : L0;
+    T *o = dst + in.offset;
+    for (int idx = threadIdx.x; idx < 9 * nodes; idx += blockDim.x) {
+        const int q = idx / nodes, j = idx - q * nodes;
+        o[q * in.plane + j] = fin[idx];
+    }
+    // Status: rare events, one atomic per reporting lane.
+    DevStatus *st = a.status + i;
+    if (first_bad != INT64_MAX) {
+        const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
+        atomicOr(&st->flags, 1u);
+        atomicMin((unsigned long long *)&st->first_step, (unsigned long long)(s0 + first_bad));
+    }
+    if (guarded != 0) {
+        atomicOr(&st->flags, 2u);
+        atomicAdd((unsigned long long *)&st->guarded, (unsigned long long)guarded);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -318,7 +469,7 @@ __device__ __forceinline__ int node3(C &f0, C &fp, C &fm, int role, C omega)
     return (nonneg_finite(f0) && nonneg_finite(fp) && nonneg_finite(fm)) ? 0 : 1;
 }
 
-template <int ST>
+template <int ST, int NT = 0>
 __device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict__ s,
                                           typename Form<ST>::T *__restrict__ d, int64_t P, int x, int nx,
                                           int bc, typename Form<ST>::C omega, typename Form<ST>::C rho0,
@@ -329,20 +480,23 @@ __device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict
     const int xm = x > 0 ? x - 1 : (wrap ? nx - 1 : 0);
     const int xp = x < nx - 1 ? x + 1 : (wrap ? 0 : nx - 1);
     const C r0 = C(2.0 / 3.0) * rho0, r1 = C(1.0 / 6.0) * rho0;
-    C f0 = load<ST>(s + x, r0, a.fp16_iscale);
-    C fp = load<ST>(s + P + xm, r1, a.fp16_iscale);
-    C fm = load<ST>(s + 2 * P + xp, r1, a.fp16_iscale);
+    using T = typename Form<ST>::T;
+    const T l0 = ldraw<T, (NT & 1) != 0>(s + x), l1 = ldraw<T, (NT & 1) != 0>(s + P + xm),
+            l2 = ldraw<T, (NT & 1) != 0>(s + 2 * P + xp);
+    C f0 = load<ST>(&l0, r0, a.fp16_iscale);
+    C fp = load<ST>(&l1, r1, a.fp16_iscale);
+    C fm = load<ST>(&l2, r1, a.fp16_iscale);
     const int role = (bc != BC_PERIODIC && (x == 0 || x == nx - 1)) ? R_WALL : R_FLUID;
     const int fl = node3<C>(f0, fp, fm, role, omega);
     if (valid) {
-        store<ST>(d + x, f0, r0, a.fp16_scale);
-        store<ST>(d + P + x, fp, r1, a.fp16_scale);
-        store<ST>(d + 2 * P + x, fm, r1, a.fp16_scale);
+        store<ST, (NT & 2) != 0>(d + x, f0, r0, a.fp16_scale);
+        store<ST, (NT & 2) != 0>(d + P + x, fp, r1, a.fp16_scale);
+        store<ST, (NT & 2) != 0>(d + 2 * P + x, fm, r1, a.fp16_scale);
     }
     return fl;
 }
 
-template <int ST, int BX, int NPT>
+template <int ST, int BX, int NPT, int NT = 0>
 __global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restrict__ src,
                                              typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
@@ -354,14 +508,14 @@ __global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restr
     for (int k = 0; k < NPT; ++k) {
         const int x = (blockIdx.x * NPT + k) * BX + (int)threadIdx.x;
         const bool valid = x < nx;
-        const int fl = step3_node<ST>(src, dst, in.plane, valid ? x : nx - 1, nx, a.bc, C(in.omega),
+        const int fl = step3_node<ST, NT>(src, dst, in.plane, valid ? x : nx - 1, nx, a.bc, C(in.omega),
                                       C(in.rho0), a, valid);
         bad = bad || (valid && fl);
     }
     report(a.status, bad, 0, a.step, a.step_base);
 }
 
-template <int ST, int BLK, int NPT>
+template <int ST, int BLK, int NPT, int NT = 0>
 __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *__restrict__ src,
                                                     typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
@@ -376,7 +530,7 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *
     for (int k = 0; k < NPT; ++k) {
         const int x = a.tile_first[t] + k * BLK + (int)threadIdx.x;
         const bool valid = x < nx;
-        const int fl = step3_node<ST>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
+        const int fl = step3_node<ST, NT>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
                                       C(in.omega), C(in.rho0), a, valid);
         bad = bad || (valid && fl);
     }
@@ -526,11 +680,25 @@ constexpr Shape kShapes[] = {
     {64, 4, 2, 1, "64x4 rows=2 xcd"},
     {64, 2, 1, 1, "64x2 rows=1 xcd"},
     {128, 1, 1, 1, "128x1 rows=1 xcd"},
+    {256, -1, 2, 1, "256 rows=2 pipelined xcd"},
+    {128, -1, 4, 1, "128 rows=4 pipelined xcd"},
+    {256, -1, 4, 1, "256 rows=4 pipelined xcd"},
+    {64, -1, 8, 1, "64 rows=8 pipelined xcd"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load nt-store"},
+    {256, -1, 2, 1, "256 rows=2 pipelined xcd nt-load"},
+    {64, 4, 2, 1, "64x4 rows=2 xcd nt-load"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-store"},
+    {256, 1, 2, 1, "256x1 rows=2 xcd nt-load nt-store"},
+    {64, 4, 2, 1, "64x4 rows=2 xcd nt-load nt-store"},
+    {256, -1, 4, 1, "256 rows=4 pipelined xcd nt-load nt-store"},
+    {128, -1, 4, 1, "128 rows=4 pipelined xcd nt-store"},
+    {256, 1, 1, 1, "256x1 rows=1 xcd nt-load nt-store"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kNumShapesOther = 3;  // MinxEnt2 / SRT instantiate the first three
+constexpr int kNumShapesOther = 3;  // the other collision rules instantiate the first three
 
-template <int ST, int CO, int BX, int BY, int RPT>
+template <int ST, int CO, int BX, int BY, int RPT, int NT = 0>
 hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
 {
     using T = typename Form<ST>::T;
@@ -538,8 +706,21 @@ hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
     const int tiles_y = (a.one.ny + BY * RPT - 1) / (BY * RPT);
     a.tiles_x = tiles_x;
     a.xcd_swizzle = swz;
-    hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT>), dim3(tiles_x * tiles_y), dim3(BX, BY), 0, s,
+    hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT, NT>), dim3(tiles_x * tiles_y), dim3(BX, BY), 0, s,
                        (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST, int CO, int BX, int RPT, int NT = 0>
+hipError_t go9pf(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int tiles_x = (a.one.nx + BX - 1) / BX;
+    const int tiles_y = (a.one.ny + RPT - 1) / RPT;
+    a.tiles_x = tiles_x;
+    a.xcd_swizzle = swz;
+    hipLaunchKernelGGL((k_d2q9_pf<ST, CO, BX, RPT, NT>), dim3(tiles_x * tiles_y), dim3(BX), 0, s, (const T *)src,
+                       (T *)dst, a);
     return hipGetLastError();
 }
 
@@ -560,6 +741,20 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
         case 5: return go9<ST, CO, 64, 4, 2>(src, dst, a, swz, s);
         case 6: return go9<ST, CO, 64, 2, 1>(src, dst, a, swz, s);
         case 7: return go9<ST, CO, 128, 1, 1>(src, dst, a, swz, s);
+        case 8: return go9pf<ST, CO, 256, 2>(src, dst, a, swz, s);
+        case 9: return go9pf<ST, CO, 128, 4>(src, dst, a, swz, s);
+        case 10: return go9pf<ST, CO, 256, 4>(src, dst, a, swz, s);
+        case 11: return go9pf<ST, CO, 64, 8>(src, dst, a, swz, s);
+        case 12: return go9<ST, CO, 256, 1, 1, 1>(src, dst, a, swz, s);
+        case 13: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
+        case 14: return go9pf<ST, CO, 256, 2, 1>(src, dst, a, swz, s);
+        case 15: return go9<ST, CO, 64, 4, 2, 1>(src, dst, a, swz, s);
+        case 16: return go9<ST, CO, 256, 1, 1, 2>(src, dst, a, swz, s);
+        case 17: return go9<ST, CO, 256, 1, 2, 3>(src, dst, a, swz, s);
+        case 18: return go9<ST, CO, 64, 4, 2, 3>(src, dst, a, swz, s);
+        case 19: return go9pf<ST, CO, 256, 4, 3>(src, dst, a, swz, s);
+        case 20: return go9pf<ST, CO, 128, 4, 2>(src, dst, a, swz, s);
+        case 21: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
         default: break;
         }
     }
@@ -584,10 +779,13 @@ template <int ST, int CO>
 hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
     using T = typename Form<ST>::T;
-    if (v == 0)
-        hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a);
-    else
-        hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 128>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 0>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 1: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 128, 0>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
+    case 2: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 3: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 2>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -613,15 +811,16 @@ constexpr Shape3 kShapes3[] = {
     {256, 4, "256 nodes=4"},
     {512, 2, "512 nodes=2"},
     {128, 4, "128 nodes=4"},
+    {256, 4, "256 nodes=4 nt-load nt-store"},
 };
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
-template <int ST, int BX, int NPT>
+template <int ST, int BX, int NPT, int NT = 0>
 hipError_t go3(const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
     using T = typename Form<ST>::T;
     const int blocks = (a.one.nx + BX * NPT - 1) / (BX * NPT);
-    hipLaunchKernelGGL((k_d1q3<ST, BX, NPT>), dim3(blocks), dim3(BX), 0, s, (const T *)src, (T *)dst, a);
+    hipLaunchKernelGGL((k_d1q3<ST, BX, NPT, NT>), dim3(blocks), dim3(BX), 0, s, (const T *)src, (T *)dst, a);
     return hipGetLastError();
 }
 
@@ -633,6 +832,7 @@ hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipSt
     case 1: return go3<ST, 256, 4>(src, dst, a, s);
     case 2: return go3<ST, 512, 2>(src, dst, a, s);
     case 3: return go3<ST, 128, 4>(src, dst, a, s);
+    case 4: return go3<ST, 256, 4, 3>(src, dst, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -643,9 +843,12 @@ struct ShapeB {
     int blk, npt;
     const char *name;
 };
-constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"}};
+constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"},
+                                {256, 1, "batch 256 nodes/block nt-load nt-store"},
+                                {256, 1, "batch 256 nodes/block nt-store"}};
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
-                                {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"}};
+                                {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
+                                {256, 4, "batch 256x4 nodes/block nt-load nt-store"}};
 
 template <int ST>
 hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
@@ -656,6 +859,7 @@ hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipS
     case 1: hipLaunchKernelGGL((k_d1q3_batch<ST, 128, 1>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
     case 2: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 4>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 3: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 8>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 4: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 4, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -695,16 +899,18 @@ int d2q9_variant_count(int coll) { return coll == CO_MINXENT4 ? kNumShapes : kNu
 const char *d2q9_variant_name(int v) { return (v >= 0 && v < kNumShapes) ? kShapes[v].name : "?"; }
 int d1q3_variant_count() { return kNumShapes3; }
 const char *d1q3_variant_name(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].name : "?"; }
-int batch_variant_count(int lattice) { return lattice == 3 ? 4 : 2; }
+constexpr int kNumB9 = sizeof(kShapesB9) / sizeof(kShapesB9[0]);
+constexpr int kNumB3 = sizeof(kShapesB3) / sizeof(kShapesB3[0]);
+int batch_variant_count(int lattice) { return lattice == 3 ? kNumB3 : kNumB9; }
 int batch_tile_nodes(int lattice, int v)
 {
-    if (lattice == 3) return (v >= 0 && v < 4) ? kShapesB3[v].blk * kShapesB3[v].npt : 0;
-    return (v >= 0 && v < 2) ? kShapesB9[v].blk * kShapesB9[v].npt : 0;
+    if (lattice == 3) return (v >= 0 && v < kNumB3) ? kShapesB3[v].blk * kShapesB3[v].npt : 0;
+    return (v >= 0 && v < kNumB9) ? kShapesB9[v].blk * kShapesB9[v].npt : 0;
 }
 const char *batch_variant_name(int lattice, int v)
 {
-    if (lattice == 3) return (v >= 0 && v < 4) ? kShapesB3[v].name : "?";
-    return (v >= 0 && v < 2) ? kShapesB9[v].name : "?";
+    if (lattice == 3) return (v >= 0 && v < kNumB3) ? kShapesB3[v].name : "?";
+    return (v >= 0 && v < kNumB9) ? kShapesB9[v].name : "?";
 }
 
 hipError_t launch_d2q9_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
@@ -728,6 +934,47 @@ hipError_t launch_d2q9_batch_step(int st, int coll, int v, const void *src, void
     case ST_F32N64: return dispatch9bc<ST_F32N64>(coll, v, src, dst, a, s);
     case ST_F32: return dispatch9bc<ST_F32>(coll, v, src, dst, a, s);
     case ST_F16DEV: return dispatch9bc<ST_F16DEV>(coll, v, src, dst, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+namespace {
+template <int ST, int CO>
+hipError_t lds_go(const void *src, void *dst, const StepArgs &a, int nsteps, int block, size_t smem, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    hipError_t e = hipFuncSetAttribute((const void *)k_d2q9_lds<ST, CO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_d2q9_lds<ST, CO>), dim3(a.ntiles), dim3(block), smem, s, (const T *)src, (T *)dst, a,
+                       nsteps);
+    return hipGetLastError();
+}
+
+template <int ST>
+hipError_t lds_coll(int coll, const void *src, void *dst, const StepArgs &a, int nsteps, int block, size_t smem,
+                    hipStream_t s)
+{
+    switch (coll) {
+    case CO_MINXENT4: return lds_go<ST, CO_MINXENT4>(src, dst, a, nsteps, block, smem, s);
+    case CO_MINXENT2: return lds_go<ST, CO_MINXENT2>(src, dst, a, nsteps, block, smem, s);
+    case CO_SRT: return lds_go<ST, CO_SRT>(src, dst, a, nsteps, block, smem, s);
+    case CO_TRT: return lds_go<ST, CO_TRT>(src, dst, a, nsteps, block, smem, s);
+    case CO_MRT: return lds_go<ST, CO_MRT>(src, dst, a, nsteps, block, smem, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_d2q9_lds(int st, int coll, const void *src, void *dst, const StepArgs &a, int nsteps, int block,
+                           size_t smem, hipStream_t s)
+{
+    if (nsteps <= 0) return hipSuccess;
+    switch (st) {
+    case ST_F64: return lds_coll<ST_F64>(coll, src, dst, a, nsteps, block, smem, s);
+    case ST_F32N64: return lds_coll<ST_F32N64>(coll, src, dst, a, nsteps, block, smem, s);
+    case ST_F32: return lds_coll<ST_F32>(coll, src, dst, a, nsteps, block, smem, s);
+    case ST_F16DEV: return lds_coll<ST_F16DEV>(coll, src, dst, a, nsteps, block, smem, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -63,6 +63,11 @@ hipError_t launch_d1q3_step(int storage, int variant, const void *src, void *dst
                             hipStream_t s);
 hipError_t launch_d1q3_batch_step(int storage, int variant, const void *src, void *dst,
                                   const StepArgs &a, hipStream_t s);
+// Batch of small D2Q9 lattices resident in LDS: one workgroup per instance
+// (a.ntiles = instances) runs nsteps steps in one launch; dst receives the
+// final state (it may equal src).
+hipError_t launch_d2q9_lds(int storage, int coll, const void *src, void *dst, const StepArgs &a, int nsteps,
+                           int block, size_t smem_bytes, hipStream_t s);
 int batch_variant_count(int lattice);
 int batch_tile_nodes(int lattice, int variant);
 const char *batch_variant_name(int lattice, int variant);

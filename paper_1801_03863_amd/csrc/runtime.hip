@@ -134,6 +134,9 @@ struct lbm_ctx {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     float scale = 1.0f, iscale = 1.0f;
     std::string arch;
+    int lds_variant = -1;  // batched D2Q9: index of the LDS-resident shape, -1 if it does not fit
+    size_t lds_bytes = 0;
+    int lds_block = 0;
 };
 
 namespace {
@@ -244,8 +247,18 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
 
 int variant_count(const lbm_ctx *c)
 {
-    if (c->batch) return lbm::batch_variant_count(c->b);
+    if (c->batch) return lbm::batch_variant_count(c->b) + (c->lds_variant >= 0 ? 1 : 0);
     return c->b == 9 ? lbm::d2q9_variant_count(c->p.collision) : lbm::d1q3_variant_count();
+}
+
+// LDS-resident batch: n steps in one launch; the state moves to
+// buf[cur ^ (n & 1)] as with n single-step launches.
+hipError_t launch_lds(lbm_ctx *c, DevStatus *status, int64_t step, int nsteps, int dst_parity_flip)
+{
+    lbm::StepArgs a = step_args(c, status, step, nullptr);
+    a.ntiles = c->n;
+    return lbm::launch_d2q9_lds(c->storage, c->p.collision, c->buf[c->cur], c->buf[c->cur ^ dst_parity_flip], a,
+                                nsteps, c->lds_block, c->lds_bytes, c->stream);
 }
 
 int capture_graph(lbm_ctx *c, int parity)
@@ -402,6 +415,19 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     CK(hipMalloc(&c->d_status, sizeof(DevStatus) * n));
     CK(hipMalloc(&c->d_status_scratch, sizeof(DevStatus) * n));
     CK(hipMalloc(&c->d_step_base, sizeof(int64_t)));
+    if (batch && c->b == 9) {
+        int64_t maxn = 0;
+        for (int i = 0; i < n; ++i) maxn = std::max<int64_t>(maxn, (int64_t)c->inst[i].nx * c->inst[i].ny);
+        int dev = 0, smem = 0;
+        CK(hipGetDevice(&dev));
+        CK(hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t need = 2 * 9 * (size_t)maxn * c->elem;
+        if (need <= (size_t)smem) {
+            c->lds_variant = lbm::batch_variant_count(9);
+            c->lds_bytes = need;
+            c->lds_block = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (maxn + 63) / 64 * 64));
+        }
+    }
     if (batch) {
         CK(hipMalloc(&c->d_inst, sizeof(Inst) * n));
         CK(hipMemcpy(c->d_inst, c->inst.data(), sizeof(Inst) * n, hipMemcpyHostToDevice));
@@ -470,6 +496,19 @@ int lbm_init_batch(const lbm_params_t *p, int32_t n, const double *rho, const do
 int lbm_step(lbm_ctx_t *c, int64_t nsteps)
 {
     if (!c || nsteps < 0) return fail(LBM_EINVAL, "bad context or step count");
+    if (c->batch && c->variant == c->lds_variant && c->lds_variant >= 0) {
+        // Persistent LDS-resident shape: no graph needed, one launch per chunk.
+        int64_t left = nsteps;
+        while (left > 0) {
+            const int chunk = (int)std::min<int64_t>(left, 1 << 20);
+            HIPCHK(launch_lds(c, c->d_status, c->steps_done, chunk, chunk & 1));
+            c->cur ^= chunk & 1;
+            c->steps_done += chunk;
+            left -= chunk;
+        }
+        c->base_synced = false;
+        return LBM_OK;
+    }
     int64_t i = 0;
     while (i < nsteps) {
         if (c->graph_chunk > 0 && nsteps - i >= c->graph_chunk) {
@@ -514,7 +553,8 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
     else HIPCHK(hipDeviceSynchronize());
     drop_graphs(c);
     c->variant = v;
-    if (c->batch && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes) return build_tiles(c, lbm::batch_tile_nodes(c->b, v));
+    if (c->batch && v != c->lds_variant && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes)
+        return build_tiles(c, lbm::batch_tile_nodes(c->b, v));
     return LBM_OK;
 }
 
@@ -523,6 +563,7 @@ int lbm_variant_count(const lbm_ctx_t *c) { return c ? variant_count(c) : 0; }
 const char *lbm_variant_name(const lbm_ctx_t *c, int32_t v)
 {
     if (!c) return "?";
+    if (c->batch && v == c->lds_variant && v >= 0) return "batch persistent, lattices resident in LDS";
     if (c->batch) return lbm::batch_variant_name(c->b, v);
     return c->b == 9 ? lbm::d2q9_variant_name(v) : lbm::d1q3_variant_name(v);
 }
@@ -561,22 +602,35 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
     for (int v = 0; v < nv; ++v) {
         int rc = lbm_set_variant(c, v);
         if (rc) return rc;
-        // Source buffer is the current state and is never written here.
+        // Source buffer is the current state and is never written here (the
+        // persistent shape runs an odd number of steps, ending in the other
+        // buffer).
+        const bool pers = c->batch && v == c->lds_variant;
+        const int preps = reps | 1;
         for (int r = 0; r < 3; ++r) {
-            lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
-            HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+            if (pers) {
+                HIPCHK(launch_lds(c, c->d_status_scratch, 0, 1, 1));
+            } else {
+                lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
+                HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+            }
         }
         float shape_best = 1e30f;
         for (int trial = 0; trial < 3; ++trial) {
             HIPCHK(hipEventRecord(e0, c->stream));
-            for (int r = 0; r < reps; ++r) {
-                lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
-                HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+            if (pers) {
+                HIPCHK(launch_lds(c, c->d_status_scratch, 0, preps, 1));
+            } else {
+                for (int r = 0; r < reps; ++r) {
+                    lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
+                    HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+                }
             }
             HIPCHK(hipEventRecord(e1, c->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (pers) ms = ms * (float)reps / (float)preps;
             shape_best = std::min(shape_best, ms);
         }
         if (shape_best < best) {

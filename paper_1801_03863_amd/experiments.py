@@ -122,7 +122,14 @@ def stability_sweep(collision, inv_taus, lids, n=17, rho0=2.7, steps=1000, preci
     z = np.zeros(m * n * n)
     ctx = B.lbm_init_batch(params, rho, z, z)
     try:
-        B.lbm_set_graph_chunk(ctx, 100)
+        # All lattices are tiny: run every step in one launch with the
+        # lattices resident in LDS when the device allows it.
+        names = [B.lbm_variant_name(ctx, v) for v in range(B.lbm_variant_count(ctx))]
+        lds = [v for v, nm in enumerate(names) if "LDS" in nm]
+        if lds:
+            B.lbm_set_variant(ctx, lds[0])
+        else:
+            B.lbm_set_graph_chunk(ctx, 100)
         B.lbm_step(ctx, steps)
         st = B.lbm_status_batch(ctx, m)
     finally:
