@@ -90,12 +90,12 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
             "fields": {"rho": r, "ux": u, "uy": v}, "status": st}
 
 
-def time_batch(B, torch, params, rho, ux, uy, steps, warmup):
+def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None):
     """Time a batched context (one launch per step over every instance)."""
     ws = torch.empty(B.lbm_workspace_bytes_batch(params), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     ctx = B.lbm_init_batch(params, rho, ux, uy, workspace=ws, stream=stream)
-    variant = B.lbm_autotune(ctx)
+    variant = B.lbm_autotune(ctx, tune_cache)
     B.lbm_step(ctx, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -138,7 +138,7 @@ def rel_errors(a, b, mask):
     return out
 
 
-def batched_cavities(B, torch, I, steps, warmup):
+def batched_cavities(B, torch, I, steps, warmup, tune_cache=None):
     """512 cavities, sides log-uniform in [32, 512], Re uniform in [100, 1e4],
     lid 0.1, FP32, one launch per step; error against the same batch in FP64."""
     import numpy as np
@@ -156,7 +156,7 @@ def batched_cavities(B, torch, I, steps, warmup):
     res = {}
     for prec in ("fp32", "fp64"):
         params = [B.make_params("d2q9", "minxent4", "cavity", prec, n, n, tau, 0.0, 0.1, 1.0) for n, tau, re in insts]
-        res[prec] = time_batch(B, torch, params, rho, ux, ux, steps, warmup)
+        res[prec] = time_batch(B, torch, params, rho, ux, ux, steps, warmup, tune_cache)
         out[prec] = rate(res[prec], steps)
     out["field_error_fp32_vs_fp64"] = rel_errors(res["fp32"]["fields"], res["fp64"]["fields"], mask)
     out["instances"] = len(insts)
@@ -183,7 +183,7 @@ def fp16_cavity(B, torch, I, steps, warmup, tune_cache):
     return out
 
 
-def fp16_tubes(B, torch, I, steps, warmup):
+def fp16_tubes(B, torch, I, steps, warmup, tune_cache=None):
     """4096 D1Q3 shock tubes, lengths log-uniform in [1024, 65536], density
     ratio in [1.5, 4], tau in [0.505, 0.6]: FP16 deviations against FP64.
     On D1Q3 the method is SRT, which breaks down for the sharpest tubes near
@@ -197,7 +197,7 @@ def fp16_tubes(B, torch, I, steps, warmup):
     for prec in ("fp16dev", "fp64"):
         params = [B.make_params("d1q3", "srt", "tube", prec, n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr))
                   for n, rl, rr, tau in tubes]
-        res[prec] = time_batch(B, torch, params, rho, ux, None, steps, warmup)
+        res[prec] = time_batch(B, torch, params, rho, ux, None, steps, warmup, tune_cache)
         out[prec] = rate(res[prec], steps)
         out[prec]["unstable_instances"] = int(sum(s_["unstable"] for s_ in res[prec]["per_instance"]))
     masks = []
@@ -258,7 +258,8 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1801_03863_amd", "tune_cache_gfx950.txt"),
+                    help="autotuner cache (entries are keyed by a hash of the kernel sources)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and FP16 workloads")
     ap.add_argument("--extra-steps", type=int, default=500)
     args = ap.parse_args()
@@ -321,10 +322,10 @@ def main():
         ref32 = time_form(B, torch, "fp32", n, tau, cfg["u_lid"], fields, args.extra_steps, args.warmup,
                           args.tune_cache)
         out["fp32"] = rate(ref32, args.extra_steps)
-        out["batched_cavities_512"] = batched_cavities(B, torch, I, args.extra_steps, args.warmup)
+        out["batched_cavities_512"] = batched_cavities(B, torch, I, args.extra_steps, args.warmup, args.tune_cache)
         out["fp16dev_cavity_8192"] = fp16_cavity(B, torch, I, min(args.extra_steps, 300), args.warmup,
                                                  args.tune_cache)
-        out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup)
+        out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup, args.tune_cache)
     out["copy_kernel_gbs"] = round(copy_bandwidth(B, torch), 1)
     out["kernel_source_sha256_16"] = digest
     if not args.no_cpu_baseline:

@@ -36,14 +36,26 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def source_id() -> str:
+    """Hash of the kernel and runtime sources; it keys the autotuner cache so
+    that entries made by other builds are ignored."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:12]
+
+
 def build_library(verbose: bool = False, jobs: int = 2) -> str:
     """Compile every HIP source for gfx950 and link liblbm.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     cc = hipcc()
+    flags = HIP_FLAGS + ["-DLBM_SOURCE_ID=\"%s\"" % source_id()]
 
     def compile_one(src):
         obj = os.path.join(BUILD_DIR, src + ".o")
-        cmd = [cc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

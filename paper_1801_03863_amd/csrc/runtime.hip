@@ -14,6 +14,10 @@
 #include "../../include/lbm.h"
 #include "kernels.hpp"
 
+#ifndef LBM_SOURCE_ID
+#define LBM_SOURCE_ID "dev"
+#endif
+
 using lbm::DevStatus;
 using lbm::Inst;
 
@@ -572,9 +576,9 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
 {
     if (!c) return fail(LBM_EINVAL, "null context");
     char key[256];
-    std::snprintf(key, sizeof(key), "%s|lat%d|prec%d|coll%d|bc%d|n%d|%dx%d|nodes%lld", c->arch.c_str(), c->b,
-                  c->p.precision, c->p.collision, c->p.bc, c->n, c->inst[0].nx, c->inst[0].ny,
-                  (long long)c->nodes);
+    std::snprintf(key, sizeof(key), "%s|%s|lat%d|prec%d|coll%d|bc%d|n%d|%dx%d|nodes%lld", LBM_SOURCE_ID,
+                  c->arch.c_str(), c->b, c->p.precision, c->p.collision, c->p.bc, c->n, c->inst[0].nx,
+                  c->inst[0].ny, (long long)c->nodes);
     if (cache_path) {
         if (FILE *fh = std::fopen(cache_path, "r")) {
             char line[512];
