@@ -89,20 +89,36 @@ __device__ __forceinline__ void batch_rcp(const double (&x)[N], double (&r)[N], 
 // s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd series through s^19
 // (truncation below 2^-54), and k ln 2 added with ln 2 split into a 32-bit
 // head and a tail (the Cody-Waite / fdlibm split).  The four divisions share
-// one reciprocal.  Error <= 2-3 ulp on both paths.
+// one reciprocal.  Arguments close to one take shorter forms (below).
+// Error <= 2-3 ulp on every path.
 __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
 {
-    // Fast path, taken when every argument is within 1/16 of one (always the
-    // case near equilibrium): t = y - 1 is exact, s = t/(2 + t) has
-    // |s| <= 0.0323 and the series through s^11 is below 2^-60.
     double t[4];
-    bool near = true;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        t[i] = y[i] - 1.0;
-        near = near && __builtin_fabs(t[i]) < 0.0625;
+    for (int i = 0; i < 4; ++i) t[i] = y[i] - 1.0;  // exact for y in [1/2, 2]
+    const double mt = __builtin_fmax(__builtin_fmax(__builtin_fabs(t[0]), __builtin_fabs(t[1])),
+                                     __builtin_fmax(__builtin_fabs(t[2]), __builtin_fabs(t[3])));
+    if (mt < 0.0078125) {
+        // Nearest tier, |t| < 2^-7 (the bulk of a smooth flow): the Taylor
+        // series ln(1 + t) = t + t^2 Q(t) with Q through the t^8 term; the
+        // first omitted term is below 2^-56 |t| / 9.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double x = t[i];
+            double q = -0.125;
+            q = __builtin_fma(q, x, 1.0 / 7.0);
+            q = __builtin_fma(q, x, -1.0 / 6.0);
+            q = __builtin_fma(q, x, 1.0 / 5.0);
+            q = __builtin_fma(q, x, -0.25);
+            q = __builtin_fma(q, x, 1.0 / 3.0);
+            q = __builtin_fma(q, x, -0.5);
+            out[i] = __builtin_fma(x * x, q, x);
+        }
+        return;
     }
-    if (near) {
+    if (mt < 0.0625) {
+        // Near tier, |t| < 1/16: s = t/(2 + t) has |s| <= 0.0323 and the
+        // atanh series through s^11 is below 2^-60.
         double den[4], rd[4], prod;
 #pragma unroll
         for (int i = 0; i < 4; ++i) den[i] = 2.0 + t[i];
@@ -280,103 +296,181 @@ __device__ __forceinline__ void collide_mrt(C (&f)[9], C be, C bp, C bq, C bs)
     f[8] = f[8] + ((dgn + (sx - sy)) - s9);
 }
 
+// True if any of the nine values has its sign bit set (negative values and
+// -0): the minimum of the high words as signed integers is negative.  Four
+// three-input integer minima instead of eight floating-point ones.
+__device__ __forceinline__ bool any_sign9(const double (&v)[9])
+{
+    int32_t h[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) h[a] = (int32_t)(__builtin_bit_cast(uint64_t, v[a]) >> 32);
+    int32_t m = h[0];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) m = m < h[a] ? m : h[a];
+    return m < 0;
+}
+
+__device__ __forceinline__ bool any_sign9(const float (&v)[9])
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o |= __builtin_bit_cast(uint32_t, v[a]);
+    return (int32_t)o < 0;
+}
+
 // MinxEnt collision with a single Newton step.  MX2 selects MinxEnt2 (only
 // e and eps free; q_x, q_y relaxed with omega2 = 1/tau2).  Returns true if
 // the node was guarded: its start point had a population <= 0 or not
 // finite, in which case f holds the start point itself (no Newton step).
-// `finite` is false if the result has an inf or NaN (the start point is
-// finite, so only the Newton increments can make it so).
+// `stable` is the stability criterion of Sec. IV.G for the result: every
+// population finite and non-negative.
 template <class C, bool MX2>
-__device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bool &finite)
+__device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bool &stable)
 {
-    // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C).
-    const C rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const C jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const C jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const C pxxyy = (f[1] + f[3]) - (f[2] + f[4]);  // sum f (vx^2 - vy^2)
-    const C pxy = (f[5] + f[7]) - (f[6] + f[8]);    // sum f vx vy
+    // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C), from
+    // shared pair sums and differences.
+    const C a13 = f[1] + f[3], a24 = f[2] + f[4], m13 = f[1] - f[3], m24 = f[2] - f[4];
+    const C d57 = f[5] + f[7], d68 = f[6] + f[8], n57 = f[5] - f[7], n68 = f[6] - f[8];
+    const C rho = (f[0] + (a13 + a24)) + (d57 + d68);
+    const C jx = m13 + (n57 - n68);
+    const C jy = m24 + (n57 + n68);
+    const C pxxyy = a13 - a24;  // sum f (vx^2 - vy^2)
+    const C pxy = d57 - d68;    // sum f vx vy
     const C irho = rcp(rho);
     const C ux = jx * irho, uy = jy * irho;
     // Relaxed stress constraints C8, C9 as deviations from equilibrium.
     const C k = C(1) - omega;
     const C q8 = C(0.25) * k * (pxxyy - (jx * ux - jy * uy));
     const C q9 = C(0.25) * k * (pxy - jx * uy);
-    // MinxEnt2: C5 and C7 relaxed with 1/tau2 (T^-1 columns = rows / 12).
-    C q5 = C(0), q7 = C(0);
-    if (MX2) {
+    // Start point: the polynomial equilibrium
+    //   W_a rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
+    // plus the non-equilibrium corrections, with the weights folded into
+    // the coefficients (rho/9 * 4.5 = rho/2, rho/36 * 4.5 = rho/8).
+    const C uxx = ux * ux, uyy = uy * uy;
+    const C b1 = C(1) - C(1.5) * (uxx + uyy);
+    const C wa = W9<C>::axis * rho, wd = W9<C>::diag * rho;
+    const C wa3 = C(1.0 / 3.0) * rho, wd3 = C(1.0 / 12.0) * rho;
+    const C wa45 = C(0.5) * rho, wd45 = C(0.125) * rho;
+    const C wab = wa * b1, wdb = wd * b1;
+    const C s = ux + uy, d = ux - uy;
+    const C ex = __builtin_fma(wa45, uxx, wab) + q8;
+    const C ey = __builtin_fma(wa45, uyy, wab) - q8;
+    const C es = __builtin_fma(wd45, s * s, wdb) + q9;
+    const C ed = __builtin_fma(wd45, d * d, wdb) - q9;
+    C f0[9];
+    f0[0] = (W9<C>::rest * rho) * b1;
+    if constexpr (MX2) {
+        // MinxEnt2: C5 and C7 relaxed with 1/tau2 (T^-1 columns = rows / 12).
         const C k2 = C(1) - omega2;
         const C m5 = C(2) * (f[3] - f[1]) + (f[5] - f[6]) + (f[8] - f[7]);
         const C m7 = C(2) * (f[4] - f[2]) + (f[5] + f[6]) - (f[7] + f[8]);
-        q5 = k2 * (m5 + jx) * C(1.0 / 12.0);
-        q7 = k2 * (m7 + jy) * C(1.0 / 12.0);
+        const C q5 = k2 * (m5 + jx) * C(1.0 / 12.0);
+        const C q7 = k2 * (m7 + jy) * C(1.0 / 12.0);
+        f0[1] = __builtin_fma(wa3, ux, ex - C(2) * q5);
+        f0[2] = __builtin_fma(wa3, uy, ey - C(2) * q7);
+        f0[3] = __builtin_fma(-wa3, ux, ex + C(2) * q5);
+        f0[4] = __builtin_fma(-wa3, uy, ey + C(2) * q7);
+        f0[5] = __builtin_fma(wd3, s, es + (q5 + q7));
+        f0[6] = __builtin_fma(-wd3, d, ed - (q5 - q7));
+        f0[7] = __builtin_fma(-wd3, s, es - (q5 + q7));
+        f0[8] = __builtin_fma(wd3, d, ed + (q5 - q7));
+    } else {
+        f0[1] = __builtin_fma(wa3, ux, ex);
+        f0[2] = __builtin_fma(wa3, uy, ey);
+        f0[3] = __builtin_fma(-wa3, ux, ex);
+        f0[4] = __builtin_fma(-wa3, uy, ey);
+        f0[5] = __builtin_fma(wd3, s, es);
+        f0[6] = __builtin_fma(-wd3, d, ed);
+        f0[7] = __builtin_fma(-wd3, s, es);
+        f0[8] = __builtin_fma(wd3, d, ed);
     }
-    // Start point: the polynomial equilibrium W_a rho (1 + e_a) plus the
-    // non-equilibrium corrections c_a.
-    const C b1 = C(1) - C(1.5) * (ux * ux + uy * uy);
-    const C s = ux + uy, d = ux - uy;
-    const C hx = C(4.5) * ux * ux + b1, hy = C(4.5) * uy * uy + b1;
-    const C hs = C(4.5) * s * s + b1, hd = C(4.5) * d * d + b1;
-    const C wr = W9<C>::rest * rho, wa = W9<C>::axis * rho, wd = W9<C>::diag * rho;
-    C f0[9];
-    f0[0] = wr * b1;
-    f0[1] = wa * (hx + C(3) * ux) + (q8 - C(2) * q5);
-    f0[2] = wa * (hy + C(3) * uy) - (q8 + C(2) * q7);
-    f0[3] = wa * (hx - C(3) * ux) + (q8 + C(2) * q5);
-    f0[4] = wa * (hy - C(3) * uy) - (q8 - C(2) * q7);
-    f0[5] = wd * (hs + C(3) * s) + (q9 + (q5 + q7));
-    f0[6] = wd * (hd - C(3) * d) - (q9 + (q5 - q7));
-    f0[7] = wd * (hs - C(3) * s) + (q9 - (q5 + q7));
-    f0[8] = wd * (hd + C(3) * d) - (q9 - (q5 - q7));
 
-    // Guard: every start population positive and finite.  The minimum
-    // catches values <= 0; the product (double) or sum (float) is not finite
-    // if any value is inf or NaN.
-    C mn = f0[0];
-#pragma unroll
-    for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f0[a]);
+    // Reciprocals r_a = 1/f0_a and the guard: every start population must be
+    // positive and finite (sign bits clear, product of all nine a positive
+    // normal number below infinity); otherwise the node keeps its start point.
+    // The gradient g = A^T ln(f0/W) is taken as the logarithms of products
+    // of population ratios, each close to one near equilibrium:
+    //  g_e   = ln( 2^24 F^2 R r0^4 ),   g_eps = ln( f0^4 F R^2 )
+    //  g_qx  = ln( (f3 r1)^2 f5 f8 r6 r7 ),  g_qy = ln( (f4 r2)^2 f5 f6 r7 r8 )
+    // with F = f5 f6 f7 f8 and R = r1 r2 r3 r4 (2^24 = prod_a W_a^(-a_e,a),
+    // the only weight term left; ln rho and the "+1" cancel because every
+    // free column sums to zero).
     C r[9];
+    C y[4];
     bool ok;
     if constexpr (sizeof(C) == 8) {
-        double prod;
-        batch_rcp<9>(f0, r, prod);
-        ok = mn > C(0) && prod > 2.2250738585072014e-308 && prod < C(__builtin_huge_val());
+        // Montgomery's simultaneous inversion over the order
+        // 5 6 7 8 1 2 3 4 0: the prefix product after four factors is F, and
+        // the running reciprocal after the first back-substitution step is
+        // 1/(F f1 f2 f3 f4), so R = F times it.
+        const double p1 = f0[5] * f0[6];
+        const double p2 = p1 * f0[7];
+        const double F = p2 * f0[8];
+        const double p4 = F * f0[1];
+        const double p5 = p4 * f0[2];
+        const double p6 = p5 * f0[3];
+        const double p7 = p6 * f0[4];
+        const double p8 = p7 * f0[0];
+        double q = rcp(p8);
+        r[0] = q * p7;
+        q = q * f0[0];
+        const double R = F * q;
+        r[4] = q * p6;
+        q = q * f0[4];
+        r[3] = q * p5;
+        q = q * f0[3];
+        r[2] = q * p4;
+        q = q * f0[2];
+        r[1] = q * F;
+        q = q * f0[1];
+        r[8] = q * p2;
+        q = q * f0[8];
+        r[7] = q * p1;
+        q = q * f0[7];
+        r[6] = q * f0[5];
+        r[5] = q * f0[6];
+        ok = !any_sign9(f0) && p8 > 2.2250738585072014e-308 && p8 < C(__builtin_huge_val());
+        const double FR = F * R;
+        const double a0 = r[0] * 64.0, a2 = a0 * a0;  // (64 r0)^4 = 2^24 r0^4
+        const double b0 = f0[0] * f0[0];
+        const double t31 = f0[3] * r[1], t42 = f0[4] * r[2];
+        y[0] = (FR * F) * (a2 * a2);
+        y[1] = (FR * R) * (b0 * b0);
+        y[2] = (t31 * t31) * ((f0[5] * f0[8]) * (r[6] * r[7]));
+        y[3] = (t42 * t42) * (p1 * (r[7] * r[8]));
     } else {
         C sum = f0[0];
 #pragma unroll
         for (int a = 1; a < 9; ++a) sum += f0[a];
+        C mn = f0[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f0[a]);
         ok = mn > C(0) && sum < C(__builtin_huge_valf());
 #pragma unroll
         for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
-    }
-    if (!ok) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) f[a] = f0[a];
-        C sm = f0[0];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) sm += f0[a];
-        finite = __builtin_fabs(sm) < C(__builtin_huge_valf());  // inf and NaN fail
-        return true;
-    }
-
-    // Gradient g = A^T ln(f0 / W), as logarithms of products of ratios:
-    //  g_e   = ln( 2^24 (f5 f6 f7 f8)^2 r0^4 r1 r2 r3 r4 )
-    //  g_eps = ln( f0^4 f5 f6 f7 f8 (r1 r2 r3 r4)^2 )
-    //  g_qx  = ln( (f3 r1)^2 f5 f8 r6 r7 ),  g_qy = ln( (f4 r2)^2 f5 f6 r7 r8 )
-    // with r_a = 1/f0_a (2^24 = prod_a W_a^(-a_e,a), the only non-zero weight
-    // term; ln rho and the "+1" cancel because the columns sum to zero).
-    C g[4];
-    {
         const C X = ((f0[5] * r[1]) * (f0[6] * r[2])) * ((f0[7] * r[3]) * (f0[8] * r[4]));
         const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
         const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));
         const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        C y[4];
         y[0] = (Pe * X) * C(16777216.0);
         y[1] = Pp * X;
         y[2] = (t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7]));
         y[3] = (t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8]));
-        ln4(y, g);
     }
+    if (!ok) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f[a] = f0[a];
+        C sm = f0[0], mn = f0[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            sm += f0[a];
+            mn = __builtin_fmin(mn, f0[a]);
+        }
+        stable = __builtin_fabs(sm) < C(__builtin_huge_valf()) && mn >= C(0);  // inf and NaN fail the sum
+        return true;
+    }
+    C g[4];
+    ln4(y, g);
 
     // Hessian H = A^T diag(r) A.
     const C Sa = (r[1] + r[2]) + (r[3] + r[4]);
@@ -410,7 +504,6 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         dy = g[3];
     }
 
-    finite = __builtin_fabs((de + dp) + (dx + dy)) < C(__builtin_huge_valf());
     // f_post = f0 - A delta.
     const C axis = de + C(2) * dp;
     const C dgn = C(2) * de + dp;
@@ -423,6 +516,11 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     f[6] = f0[6] - (dgn - (dx - dy));
     f[7] = f0[7] - (dgn - (dx + dy));
     f[8] = f0[8] - (dgn + (dx - dy));
+    // Stable: finite (f0 is finite, so only the increments can make it
+    // otherwise) and no sign bit set.  f0 > 0 here, and a sum with a
+    // positive operand is never -0 under round-to-nearest, so the sign bits
+    // mark exactly the negative results.
+    stable = __builtin_fabs((de + dp) + (dx + dy)) < C(__builtin_huge_valf()) && !any_sign9(f);
     return false;
 }
 

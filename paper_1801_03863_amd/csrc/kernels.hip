@@ -114,33 +114,78 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
     }
 }
 
-// Pull the nine populations that stream into node (x, y).  Plane bases are
-// uniform (scalar registers); per-lane addressing is one 32-bit byte offset
-// per row/column combination, so loads use the scalar-base + vector-offset
+// Pull the nine raw stored populations that stream into node (x, y).  Row
+// bases are uniform when y is (scalar registers); per-lane addressing is one
+// 32-bit column byte offset, so loads take the scalar-base + vector-offset
 // form.
+template <int ST, bool NT = false>
+__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
+                                          const Nb &n, typename Form<ST>::T (&r)[9])
+{
+    using T = typename Form<ST>::T;
+    const int64_t PB = P * (int64_t)sizeof(T);
+    const uint32_t E = sizeof(T);
+    const char *bc_ = (const char *)s + (int64_t)y * nx * E;
+    const char *bm_ = (const char *)s + (int64_t)n.ym * nx * E;
+    const char *bp_ = (const char *)s + (int64_t)n.yp * nx * E;
+    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
+    r[0] = ldraw<T, NT>((const T *)(bc_ + cc));
+    r[1] = ldraw<T, NT>((const T *)((bc_ + PB) + cm));
+    r[2] = ldraw<T, NT>((const T *)((bm_ + 2 * PB) + cc));
+    r[3] = ldraw<T, NT>((const T *)((bc_ + 3 * PB) + cp));
+    r[4] = ldraw<T, NT>((const T *)((bp_ + 4 * PB) + cc));
+    r[5] = ldraw<T, NT>((const T *)((bm_ + 5 * PB) + cm));
+    r[6] = ldraw<T, NT>((const T *)((bm_ + 6 * PB) + cp));
+    r[7] = ldraw<T, NT>((const T *)((bp_ + 7 * PB) + cp));
+    r[8] = ldraw<T, NT>((const T *)((bp_ + 8 * PB) + cm));
+}
+
+// Pull and widen the nine populations that stream into node (x, y).
 template <int ST, bool NT = false>
 __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
                                       const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
                                       typename Form<ST>::C (&f)[9])
 {
-    using T = typename Form<ST>::T;
-    const char *b = (const char *)s;
-    const int64_t PB = P * (int64_t)sizeof(T);
-    const uint32_t E = sizeof(T);
-    const uint32_t rc = (uint32_t)(y * nx) * E, rm = (uint32_t)(n.ym * nx) * E, rp = (uint32_t)(n.yp * nx) * E;
-    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
-    T r[9];
-    r[0] = ldraw<T, NT>((const T *)(b + (rc + cc)));
-    r[1] = ldraw<T, NT>((const T *)(b + PB + (rc + cm)));
-    r[2] = ldraw<T, NT>((const T *)(b + 2 * PB + (rm + cc)));
-    r[3] = ldraw<T, NT>((const T *)(b + 3 * PB + (rc + cp)));
-    r[4] = ldraw<T, NT>((const T *)(b + 4 * PB + (rp + cc)));
-    r[5] = ldraw<T, NT>((const T *)(b + 5 * PB + (rm + cm)));
-    r[6] = ldraw<T, NT>((const T *)(b + 6 * PB + (rm + cp)));
-    r[7] = ldraw<T, NT>((const T *)(b + 7 * PB + (rp + cp)));
-    r[8] = ldraw<T, NT>((const T *)(b + 8 * PB + (rp + cm)));
+    typename Form<ST>::T r[9];
+    pull9_raw<ST, NT>(s, P, x, y, nx, n, r);
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = load<ST>(&r[q], ref[q], iscale);
+}
+
+// Write the nine post-collision populations of node (x, y) of a row that is
+// uniform across the wave.  The row base is read from the first lane so that
+// it lives in scalar registers, and each store takes the scalar-base +
+// 32-bit vector-offset form of a global store.
+template <int ST, bool NT = false>
+__device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
+                                         const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
+                                         float scale)
+{
+    using T = typename Form<ST>::T;
+    using GT = __attribute__((address_space(1))) T;
+    const uint64_t v = (uint64_t)d + (uint64_t)((int64_t)y * nx * (int64_t)sizeof(T));
+    // readfirstlane returns a signed int: each half goes through uint32_t so
+    // that widening zero-extends it.
+    const uint32_t vhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    const uint32_t vlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint64_t b = ((uint64_t)vhi << 32) | (uint64_t)vlo;
+    const uint64_t PB = (uint64_t)P * sizeof(T);
+    // The empty asm statements keep the lane offset and each plane base
+    // opaque, so the compiler can neither share a widened offset with the
+    // loads nor fold it into a 64-bit vector address.
+    uint32_t o = (uint32_t)x * (uint32_t)sizeof(T);
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        uint64_t bq = b + q * PB;
+        asm volatile("" : "+s"(bq));
+        GT *p = (GT *)(bq + (uint64_t)o);
+        T t;
+        if constexpr (ST == ST_F16DEV) t = T((f[q] - ref[q]) * scale);
+        else t = T(f[q]);
+        if constexpr (NT) __builtin_nontemporal_store(t, p);
+        else *p = t;
+    }
 }
 
 // Write the nine post-collision populations of node index i.
@@ -179,12 +224,8 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
     // minimum catches negatives; inf and NaN are caught by the Newton
     // increments (MinxEnt) or by the sum (the other rules).
     if constexpr (CO == CO_MINXENT4 || CO == CO_MINXENT2) {
-        bool fin = true;
-        const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2), fin);
-        C mn = f[0];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f[a]);
-        const bool ok = fin && mn >= C(0);
+        bool ok = true;
+        const bool g = collide_minxent<C, CO == CO_MINXENT2>(f, C(in.omega), C(in.omega2), ok);
         return (g ? 2 : 0) | (ok ? 0 : 1);
     } else {
         if constexpr (CO == CO_SRT) {
@@ -203,6 +244,30 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
         const bool ok = mn >= C(0) && sm < C(__builtin_huge_valf());
         return ok ? 0 : 1;
     }
+}
+
+// Role collision of one node of a non-lid row that is uniform across the
+// wave: only the two side-wall lanes diverge.
+template <int ST, int CO>
+__device__ __forceinline__ int node9_row(typename Form<ST>::C (&f)[9], int x, int y, int nx, int ny, int bc,
+                                         const Inst &in)
+{
+    const bool wall_row = (bc == BC_CAVITY && y == 0) || (bc == BC_BOX && (y == 0 || y == ny - 1));
+    const bool wall = wall_row || (bc != BC_PERIODIC && (x == 0 || x == nx - 1));
+    return node9<ST, CO>(f, wall ? R_WALL : R_FLUID, in);
+}
+
+// The cavity's lid row (uniform across the wave): every node takes the lid
+// equilibrium, which needs no loads.
+template <int ST, bool NT = false>
+__device__ __forceinline__ void push_lid(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
+                                         const Inst &in, const typename Form<ST>::C (&ref)[9], float scale)
+{
+    using C = typename Form<ST>::C;
+    C f[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) f[a] = C(in.lid[a]);
+    push9_xy<ST, NT>(d, P, x, y, nx, f, ref, scale);
 }
 
 // Wave-level status update: one atomic per wave and kind.
@@ -256,16 +321,21 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
     int guarded = 0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int y = (ty * RPT + k) * BY + (int)threadIdx.y;
-        if (y >= ny) break;  // wave-uniform: a wave lies in one row
+        // A wave never spans two rows (BX is a multiple of 64), so y is
+        // wave-uniform; saying so keeps all row logic in scalar registers.
+        const int y = __builtin_amdgcn_readfirstlane((ty * RPT + k) * BY + (int)threadIdx.y);
+        if (y >= ny) break;
+        if (a.bc == BC_CAVITY && y == ny - 1) {
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            continue;
+        }
         const Nb n = neighbours(xs, y, nx, ny, a.bc);
         C f[9];
         pull9<ST, (NT & 1) != 0>(src, P, xs, y, nx, n, ref, a.fp16_iscale, f);
-        const int role = role9(xs, y, nx, ny, a.bc);
-        const int fl = node9<ST, CO>(f, role, in);
+        const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         bad = bad || (xin && (fl & 1));
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9<ST, (NT & 2) != 0>(dst, P, y * nx + x, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -274,27 +344,6 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
 // each thread issues the raw loads of its next row before computing the
 // current one, so nine loads per thread are always in flight while the VALU
 // works.  Same per-node arithmetic as k_d2q9 (bitwise identical results).
-template <int ST, bool NT = false>
-__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
-                                          const Nb &n, typename Form<ST>::T (&r)[9])
-{
-    using T = typename Form<ST>::T;
-    const char *b = (const char *)s;
-    const int64_t PB = P * (int64_t)sizeof(T);
-    const uint32_t E = sizeof(T);
-    const uint32_t rc = (uint32_t)(y * nx) * E, rm = (uint32_t)(n.ym * nx) * E, rp = (uint32_t)(n.yp * nx) * E;
-    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
-    r[0] = ldraw<T, NT>((const T *)(b + (rc + cc)));
-    r[1] = ldraw<T, NT>((const T *)(b + PB + (rc + cm)));
-    r[2] = ldraw<T, NT>((const T *)(b + 2 * PB + (rm + cc)));
-    r[3] = ldraw<T, NT>((const T *)(b + 3 * PB + (rc + cp)));
-    r[4] = ldraw<T, NT>((const T *)(b + 4 * PB + (rp + cc)));
-    r[5] = ldraw<T, NT>((const T *)(b + 5 * PB + (rm + cm)));
-    r[6] = ldraw<T, NT>((const T *)(b + 6 * PB + (rm + cp)));
-    r[7] = ldraw<T, NT>((const T *)(b + 7 * PB + (rp + cp)));
-    r[8] = ldraw<T, NT>((const T *)(b + 8 * PB + (rp + cm)));
-}
-
 template <int ST, int CO, int BX, int RPT, int NT = 0>
 __global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__restrict__ src,
                                                 typename Form<ST>::T *__restrict__ dst, StepArgs a)
@@ -326,11 +375,14 @@ __global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__re
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         if (k + 1 < RPT && y + 1 < ny)
             pull9_raw<ST, (NT & 1) != 0>(src, P, xs, y + 1, nx, neighbours(xs, y + 1, nx, ny, a.bc), raw);
-        const int role = role9(xs, y, nx, ny, a.bc);
-        const int fl = node9<ST, CO>(f, role, in);
+        if (a.bc == BC_CAVITY && y == ny - 1) {
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            continue;
+        }
+        const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         bad = bad || (xin && (fl & 1));
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9<ST, (NT & 2) != 0>(dst, P, y * nx + x, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
