@@ -63,50 +63,25 @@ __device__ __forceinline__ double rcp1(double x)
 
 __device__ __forceinline__ float rcp1(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Reciprocals of N positive values with a single hardware reciprocal
-// (Montgomery's simultaneous inversion): prefix products, one full-precision
-// reciprocal of the total, then back-substitution.  The caller guarantees
-// the total product is a positive normal number.
-template <int N>
-__device__ __forceinline__ void batch_rcp(const double (&x)[N], double (&r)[N], double &prod)
+// ln(1 + t) of four doubles t > -1 (finite).  Arguments close to zero take
+// short series (below); otherwise argument reduction y = 1 + t = m 2^k with
+// m in [sqrt(1/2), sqrt(2)), then ln m = 2 atanh(s) with s = (m - 1)/(m + 1),
+// |s| <= 0.1716, summed as the odd series through s^19 (truncation below
+// 2^-54), and k ln 2 added with ln 2 split into a 32-bit head and a tail
+// (the Cody-Waite / fdlibm split).  Error <= 2-3 ulp on every path (the
+// general path rounds 1 + t once more).
+__device__ __forceinline__ void ln1p4(const double (&t)[4], double (&out)[4])
 {
-    double p[N];
-    p[0] = x[0];
-#pragma unroll
-    for (int i = 1; i < N; ++i) p[i] = p[i - 1] * x[i];
-    prod = p[N - 1];
-    double q = rcp(p[N - 1]);
-#pragma unroll
-    for (int i = N - 1; i > 0; --i) {
-        r[i] = q * p[i - 1];
-        q = q * x[i];
-    }
-    r[0] = q;
-}
-
-// Natural logarithms of four positive finite doubles.  Argument reduction
-// y = m 2^k with m in [sqrt(1/2), sqrt(2)), then ln m = 2 atanh(s) with
-// s = (m - 1)/(m + 1), |s| <= 0.1716, summed as the odd series through s^19
-// (truncation below 2^-54), and k ln 2 added with ln 2 split into a 32-bit
-// head and a tail (the Cody-Waite / fdlibm split).  The four divisions share
-// one reciprocal.  Arguments close to one take shorter forms (below).
-// Error <= 2-3 ulp on every path.
-__device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
-{
-    double t[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) t[i] = y[i] - 1.0;  // exact for y in [1/2, 2]
     const double mt = __builtin_fmax(__builtin_fmax(__builtin_fabs(t[0]), __builtin_fabs(t[1])),
                                      __builtin_fmax(__builtin_fabs(t[2]), __builtin_fabs(t[3])));
-    if (mt < 0.0078125) {
-        // Nearest tier, |t| < 2^-7 (the bulk of a smooth flow): the Taylor
-        // series ln(1 + t) = t + t^2 Q(t) with Q through the t^8 term; the
-        // first omitted term is below 2^-56 |t| / 9.
+    if (mt < 0.00390625) {
+        // Nearest tier, |t| < 2^-8 (the bulk of a smooth flow): the Taylor
+        // series ln(1 + t) = t + t^2 Q(t) with Q through the t^7 term; the
+        // first omitted term is below 2^-56 |t| / 8.
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const double x = t[i];
-            double q = -0.125;
-            q = __builtin_fma(q, x, 1.0 / 7.0);
+            double q = 1.0 / 7.0;
             q = __builtin_fma(q, x, -1.0 / 6.0);
             q = __builtin_fma(q, x, 1.0 / 5.0);
             q = __builtin_fma(q, x, -0.25);
@@ -116,16 +91,16 @@ __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
         }
         return;
     }
+    // The two remaining tiers are rare (steep gradients); they take one
+    // reciprocal per value rather than a shared one, which keeps few values
+    // live: the register budget of the whole kernel is set by its busiest
+    // point, and these paths must not be it.
     if (mt < 0.0625) {
         // Near tier, |t| < 1/16: s = t/(2 + t) has |s| <= 0.0323 and the
         // atanh series through s^11 is below 2^-60.
-        double den[4], rd[4], prod;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) den[i] = 2.0 + t[i];
-        batch_rcp<4>(den, rd, prod);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double s = t[i] * rd[i];
+            const double s = t[i] * rcp(2.0 + t[i]);
             const double z = s * s;
             double p = 1.0 / 13.0;
             p = __builtin_fma(p, z, 1.0 / 11.0);
@@ -138,21 +113,15 @@ __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
         }
         return;
     }
-    double m[4], den[4], rd[4], kd[4], prod;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        double mi = __builtin_amdgcn_frexp_mant(y[i]);  // [0.5, 1)
-        int k = __builtin_amdgcn_frexp_exp(y[i]);
-        const bool lo = mi < 0.70710678118654752440;
-        mi = lo ? mi + mi : mi;
-        kd[i] = (double)(lo ? k - 1 : k);
-        m[i] = mi;
-        den[i] = mi + 1.0;
-    }
-    batch_rcp<4>(den, rd, prod);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double s = (m[i] - 1.0) * rd[i];
+        const double y = 1.0 + t[i];
+        double m = __builtin_amdgcn_frexp_mant(y);  // [0.5, 1)
+        const int k = __builtin_amdgcn_frexp_exp(y);
+        const bool lo = m < 0.70710678118654752440;
+        m = lo ? m + m : m;
+        const double kd = (double)(lo ? k - 1 : k);
+        const double s = (m - 1.0) * rcp(m + 1.0);
         const double z = s * s;
         double p = 1.0 / 19.0;
         p = __builtin_fma(p, z, 1.0 / 17.0);
@@ -165,15 +134,14 @@ __device__ __forceinline__ void ln4(const double (&y)[4], double (&out)[4])
         p = __builtin_fma(p, z, 1.0 / 3.0);
         const double tt = s + s;
         const double lnm = __builtin_fma(tt * z, p, tt);
-        out[i] = __builtin_fma(kd[i], 6.93147180369123816490e-01,
-                               __builtin_fma(kd[i], 1.90821492927058770002e-10, lnm));
+        out[i] = __builtin_fma(kd, 6.93147180369123816490e-01, __builtin_fma(kd, 1.90821492927058770002e-10, lnm));
     }
 }
 
-__device__ __forceinline__ void ln4(const float (&y)[4], float (&out)[4])
+__device__ __forceinline__ void ln1p4(const float (&t)[4], float (&out)[4])
 {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[i] = logf(y[i]);
+    for (int i = 0; i < 4; ++i) out[i] = logf(1.0f + t[i]);
 }
 
 
@@ -396,7 +364,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     // the only weight term left; ln rho and the "+1" cancel because every
     // free column sums to zero).
     C r[9];
-    C y[4];
+    C y[4];  // y_i - 1 for the four products
     bool ok;
     if constexpr (sizeof(C) == 8) {
         // Montgomery's simultaneous inversion over the order
@@ -434,10 +402,11 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         const double a0 = r[0] * 64.0, a2 = a0 * a0;  // (64 r0)^4 = 2^24 r0^4
         const double b0 = f0[0] * f0[0];
         const double t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        y[0] = (FR * F) * (a2 * a2);
-        y[1] = (FR * R) * (b0 * b0);
-        y[2] = (t31 * t31) * ((f0[5] * f0[8]) * (r[6] * r[7]));
-        y[3] = (t42 * t42) * (p1 * (r[7] * r[8]));
+        // y_i - 1 with the last product fused (one rounding).
+        y[0] = __builtin_fma(FR * F, a2 * a2, -1.0);
+        y[1] = __builtin_fma(FR * R, b0 * b0, -1.0);
+        y[2] = __builtin_fma(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), -1.0);
+        y[3] = __builtin_fma(t42 * t42, p1 * (r[7] * r[8]), -1.0);
     } else {
         C sum = f0[0];
 #pragma unroll
@@ -452,10 +421,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
         const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));
         const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        y[0] = (Pe * X) * C(16777216.0);
-        y[1] = Pp * X;
-        y[2] = (t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7]));
-        y[3] = (t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8]));
+        y[0] = (Pe * X) * C(16777216.0) - C(1);
+        y[1] = Pp * X - C(1);
+        y[2] = (t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7])) - C(1);
+        y[3] = (t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8])) - C(1);
     }
     if (!ok) {
 #pragma unroll
@@ -470,11 +439,13 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         return true;
     }
     C g[4];
-    ln4(y, g);
+    ln1p4(y, g);
 
-    // Hessian H = A^T diag(r) A.
-    const C Sa = (r[1] + r[2]) + (r[3] + r[4]);
-    const C Sd = (r[5] + r[6]) + (r[7] + r[8]);
+    // Hessian H = A^T diag(r) A, from pair sums and differences of the r.
+    const C r13 = r[1] + r[3], r24 = r[2] + r[4], s13 = r[1] - r[3], s24 = r[2] - r[4];
+    const C r57 = r[5] + r[7], r68 = r[6] + r[8], s57 = r[5] - r[7], s68 = r[6] - r[8];
+    const C Sa = r13 + r24;
+    const C Sd = r57 + r68;
     Sym4<C> h;
     h.ee = C(16) * r[0] + Sa + C(4) * Sd;
     h.ep = C(2) * (Sa + Sd) - C(16) * r[0];
@@ -488,15 +459,15 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         de = (h.pp * g[0] - h.ep * g[1]) * idet;
         dp = (h.ee * g[1] - h.ep * g[0]) * idet;
     } else {
-        const C Dx = (r[5] + r[8]) - (r[6] + r[7]);
-        const C Dy = (r[5] + r[6]) - (r[7] + r[8]);
-        h.ex = C(2) * ((r[1] - r[3]) + Dx);
-        h.px = C(4) * (r[1] - r[3]) + Dx;
-        h.ey = C(2) * ((r[2] - r[4]) + Dy);
-        h.py = C(4) * (r[2] - r[4]) + Dy;
-        h.xx = C(4) * (r[1] + r[3]) + Sd;
-        h.yy = C(4) * (r[2] + r[4]) + Sd;
-        h.xy = (r[5] + r[7]) - (r[6] + r[8]);
+        const C Dx = s57 - s68;  // r5 - r6 - r7 + r8
+        const C Dy = s57 + s68;  // r5 + r6 - r7 - r8
+        h.ex = C(2) * (s13 + Dx);
+        h.px = C(4) * s13 + Dx;
+        h.ey = C(2) * (s24 + Dy);
+        h.py = C(4) * s24 + Dy;
+        h.xx = C(4) * r13 + Sd;
+        h.yy = C(4) * r24 + Sd;
+        h.xy = r57 - r68;
         ldlt_solve4(h, g);
         de = g[0];
         dp = g[1];

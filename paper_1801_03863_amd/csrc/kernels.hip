@@ -114,21 +114,21 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
     }
 }
 
-// Pull the nine raw stored populations that stream into node (x, y).  Row
-// bases are uniform when y is (scalar registers); per-lane addressing is one
-// 32-bit column byte offset, so loads take the scalar-base + vector-offset
-// form.
+// Pull the nine raw populations of node (x, y) given the column byte offsets
+// of x and of its two neighbours.  Row bases are uniform when the rows are
+// (scalar registers), so the loads take the scalar-base + 32-bit
+// vector-offset form.
 template <int ST, bool NT = false>
-__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
-                                          const Nb &n, typename Form<ST>::T (&r)[9])
+__device__ __forceinline__ void pull9_cols(const typename Form<ST>::T *__restrict__ s, int64_t P, int y, int ym,
+                                           int yp, int nx, uint32_t cc, uint32_t cm, uint32_t cp,
+                                           typename Form<ST>::T (&r)[9])
 {
     using T = typename Form<ST>::T;
     const int64_t PB = P * (int64_t)sizeof(T);
-    const uint32_t E = sizeof(T);
-    const char *bc_ = (const char *)s + (int64_t)y * nx * E;
-    const char *bm_ = (const char *)s + (int64_t)n.ym * nx * E;
-    const char *bp_ = (const char *)s + (int64_t)n.yp * nx * E;
-    const uint32_t cc = (uint32_t)x * E, cm = (uint32_t)n.xm * E, cp = (uint32_t)n.xp * E;
+    const int64_t RB = (int64_t)nx * (int64_t)sizeof(T);
+    const char *bc_ = (const char *)s + (int64_t)y * RB;
+    const char *bm_ = (const char *)s + (int64_t)ym * RB;
+    const char *bp_ = (const char *)s + (int64_t)yp * RB;
     r[0] = ldraw<T, NT>((const T *)(bc_ + cc));
     r[1] = ldraw<T, NT>((const T *)((bc_ + PB) + cm));
     r[2] = ldraw<T, NT>((const T *)((bm_ + 2 * PB) + cc));
@@ -138,6 +138,37 @@ __device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict
     r[6] = ldraw<T, NT>((const T *)((bm_ + 6 * PB) + cp));
     r[7] = ldraw<T, NT>((const T *)((bp_ + 7 * PB) + cp));
     r[8] = ldraw<T, NT>((const T *)((bp_ + 8 * PB) + cm));
+}
+
+// Column byte offsets of a node's own column and its two neighbours.  In a
+// tile that touches neither side of the lattice the neighbours are x -+ 1
+// for every boundary kind, so only the two edge tiles of a row (a uniform
+// test) evaluate the wrap/clamp rule.
+struct Cols {
+    uint32_t cc, cm, cp;
+};
+
+__device__ __forceinline__ Cols columns(int xs, bool edge_tile, int nx, int bc, uint32_t E)
+{
+    Cols c;
+    c.cc = (uint32_t)xs * E;
+    c.cm = c.cc - E;
+    c.cp = c.cc + E;
+    if (edge_tile) {
+        const Nb n = neighbours(xs, 0, nx, 1, bc);
+        c.cm = (uint32_t)n.xm * E;
+        c.cp = (uint32_t)n.xp * E;
+    }
+    return c;
+}
+
+// Pull the nine raw stored populations that stream into node (x, y).
+template <int ST, bool NT = false>
+__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
+                                          const Nb &n, typename Form<ST>::T (&r)[9])
+{
+    const uint32_t E = sizeof(typename Form<ST>::T);
+    pull9_cols<ST, NT>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
 }
 
 // Pull and widen the nine populations that stream into node (x, y).
@@ -296,25 +327,45 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// Tile (tx, ty) of this block.  The grid is (tiles_x, tiles_y), or one
+// dimension of tiles_x * tiles_y blocks when tiles_y exceeds the grid's y
+// limit.  In dispatch order (x fastest) the hardware deals blocks
+// round-robin to the eight XCDs; with the swizzle the linear block index is
+// remapped so that each XCD works on a contiguous band of rows.
+__device__ __forceinline__ void tile_of_block(int swizzle, int tiles_x, int &tx, int &ty)
+{
+    if (!swizzle && (int)gridDim.x == tiles_x) {
+        tx = blockIdx.x;
+        ty = blockIdx.y;
+        return;
+    }
+    int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (swizzle) b = xcd_remap(b, gridDim.x * gridDim.y);
+    ty = b / tiles_x;
+    tx = b - ty * tiles_x;
+}
+
 // --------------------------------------------------------------------------
 // D2Q9, one lattice.  Block = BX x BY threads (BX a multiple of 64, so a wave
 // never spans two rows); it covers BX columns and BY*RPT rows.
 // --------------------------------------------------------------------------
 
-template <int ST, int CO, int BX, int BY, int RPT, int NT = 0>
-__global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__restrict__ src,
-                                                 typename Form<ST>::T *__restrict__ dst, StepArgs a)
+// WPE > 0 asks the compiler for at least WPE waves per SIMD (a register
+// budget of 512/WPE VGPRs), trading registers for occupancy.
+template <int ST, int CO, int BX, int BY, int RPT, int NT = 0, int WPE = 0>
+__global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
     using C = typename Form<ST>::C;
     const Inst &in = a.one;
     const int nx = in.nx, ny = in.ny;
     const int64_t P = in.plane;
-    int b = blockIdx.x;
-    if (a.xcd_swizzle) b = xcd_remap(b, gridDim.x);
-    const int tx = b % a.tiles_x, ty = b / a.tiles_x;
+    int tx, ty;
+    tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
     const int x = tx * BX + (int)threadIdx.x;
     const bool xin = x < nx;
     const int xs = xin ? x : nx - 1;
+    const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(typename Form<ST>::T));
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     bool bad = false;
@@ -329,9 +380,14 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
             if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
             continue;
         }
-        const Nb n = neighbours(xs, y, nx, ny, a.bc);
+        const Nb n = neighbours(0, y, 1, ny, a.bc);  // rows only
         C f[9];
-        pull9<ST, (NT & 1) != 0>(src, P, xs, y, nx, n, ref, a.fp16_iscale, f);
+        {
+            typename Form<ST>::T raw[9];
+            pull9_cols<ST, (NT & 1) != 0>(src, P, y, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
+        }
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         bad = bad || (xin && (fl & 1));
         guarded += __popcll(__ballot(xin && (fl & 2)));
@@ -344,8 +400,8 @@ __global__ __launch_bounds__(BX *BY) void k_d2q9(const typename Form<ST>::T *__r
 // each thread issues the raw loads of its next row before computing the
 // current one, so nine loads per thread are always in flight while the VALU
 // works.  Same per-node arithmetic as k_d2q9 (bitwise identical results).
-template <int ST, int CO, int BX, int RPT, int NT = 0>
-__global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__restrict__ src,
+template <int ST, int CO, int BX, int RPT, int NT = 0, int WPE = 0>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_d2q9_pf(const typename Form<ST>::T *__restrict__ src,
                                                 typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
     using C = typename Form<ST>::C;
@@ -353,19 +409,22 @@ __global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__re
     const Inst &in = a.one;
     const int nx = in.nx, ny = in.ny;
     const int64_t P = in.plane;
-    int b = blockIdx.x;
-    if (a.xcd_swizzle) b = xcd_remap(b, gridDim.x);
-    const int tx = b % a.tiles_x, ty = b / a.tiles_x;
+    int tx, ty;
+    tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
     const int x = tx * BX + (int)threadIdx.x;
     const bool xin = x < nx;
     const int xs = xin ? x : nx - 1;
     const int y0 = ty * RPT;
+    const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(T));
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     bool bad = false;
     int guarded = 0;
     T raw[9];
-    pull9_raw<ST, (NT & 1) != 0>(src, P, xs, y0, nx, neighbours(xs, y0, nx, ny, a.bc), raw);
+    {
+        const Nb n = neighbours(0, y0, 1, ny, a.bc);  // rows only
+        pull9_cols<ST, (NT & 1) != 0>(src, P, y0, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+    }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int y = y0 + k;
@@ -373,8 +432,10 @@ __global__ __launch_bounds__(BX) void k_d2q9_pf(const typename Form<ST>::T *__re
         C f[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
-        if (k + 1 < RPT && y + 1 < ny)
-            pull9_raw<ST, (NT & 1) != 0>(src, P, xs, y + 1, nx, neighbours(xs, y + 1, nx, ny, a.bc), raw);
+        if (k + 1 < RPT && y + 1 < ny) {
+            const Nb n = neighbours(0, y + 1, 1, ny, a.bc);  // rows only
+            pull9_cols<ST, (NT & 1) != 0>(src, P, y + 1, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+        }
         if (a.bc == BC_CAVITY && y == ny - 1) {
             if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
             continue;
@@ -727,30 +788,28 @@ constexpr Shape kShapes[] = {
     {256, 1, 1, 0, "256x1 rows=1 linear"},
     {256, 1, 1, 1, "256x1 rows=1 xcd"},
     {64, 4, 1, 1, "64x4 rows=1 xcd"},
-    {128, 2, 1, 1, "128x2 rows=1 xcd"},
-    {256, 1, 2, 1, "256x1 rows=2 xcd"},
-    {64, 4, 2, 1, "64x4 rows=2 xcd"},
-    {64, 2, 1, 1, "64x2 rows=1 xcd"},
-    {128, 1, 1, 1, "128x1 rows=1 xcd"},
-    {256, -1, 2, 1, "256 rows=2 pipelined xcd"},
-    {128, -1, 4, 1, "128 rows=4 pipelined xcd"},
-    {256, -1, 4, 1, "256 rows=4 pipelined xcd"},
-    {64, -1, 8, 1, "64 rows=8 pipelined xcd"},
-    {256, 1, 1, 0, "256x1 rows=1 linear nt-load"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load nt-store"},
-    {256, -1, 2, 1, "256 rows=2 pipelined xcd nt-load"},
-    {64, 4, 2, 1, "64x4 rows=2 xcd nt-load"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-store"},
-    {256, 1, 2, 1, "256x1 rows=2 xcd nt-load nt-store"},
-    {64, 4, 2, 1, "64x4 rows=2 xcd nt-load nt-store"},
-    {256, -1, 4, 1, "256 rows=4 pipelined xcd nt-load nt-store"},
-    {128, -1, 4, 1, "128 rows=4 pipelined xcd nt-store"},
     {256, 1, 1, 1, "256x1 rows=1 xcd nt-load nt-store"},
+    {256, -1, 4, 1, "256 rows=4 pipelined xcd nt-load nt-store"},
+    {64, 4, 2, 1, "64x4 rows=2 xcd nt-load nt-store"},
+    {256, -1, 2, 1, "256 rows=2 pipelined xcd nt-load"},
+    {128, -1, 4, 1, "128 rows=4 pipelined xcd nt-store"},
+    {256, 1, 2, 1, "256x1 rows=2 xcd nt-load nt-store"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load nt-store waves>=6"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load nt-store waves>=8"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-store waves>=6"},
+    {256, 1, 1, 1, "256x1 rows=1 xcd nt-load nt-store waves>=6"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load nt-store waves>=7"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load"},
+    {128, 1, 1, 0, "128x1 rows=1 linear nt-load nt-store"},
+    {512, 1, 1, 0, "512x1 rows=1 linear nt-load nt-store"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
 constexpr int kNumShapesOther = 3;  // the other collision rules instantiate the first three
 
-template <int ST, int CO, int BX, int BY, int RPT, int NT = 0>
+template <int ST, int CO, int BX, int BY, int RPT, int NT = 0, int WPE = 0>
 hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
 {
     using T = typename Form<ST>::T;
@@ -758,12 +817,13 @@ hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
     const int tiles_y = (a.one.ny + BY * RPT - 1) / (BY * RPT);
     a.tiles_x = tiles_x;
     a.xcd_swizzle = swz;
-    hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT, NT>), dim3(tiles_x * tiles_y), dim3(BX, BY), 0, s,
+    const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
+    hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT, NT, WPE>), grid, dim3(BX, BY), 0, s,
                        (const T *)src, (T *)dst, a);
     return hipGetLastError();
 }
 
-template <int ST, int CO, int BX, int RPT, int NT = 0>
+template <int ST, int CO, int BX, int RPT, int NT = 0, int WPE = 0>
 hipError_t go9pf(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
 {
     using T = typename Form<ST>::T;
@@ -771,8 +831,9 @@ hipError_t go9pf(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
     const int tiles_y = (a.one.ny + RPT - 1) / RPT;
     a.tiles_x = tiles_x;
     a.xcd_swizzle = swz;
-    hipLaunchKernelGGL((k_d2q9_pf<ST, CO, BX, RPT, NT>), dim3(tiles_x * tiles_y), dim3(BX), 0, s, (const T *)src,
-                       (T *)dst, a);
+    const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
+    hipLaunchKernelGGL((k_d2q9_pf<ST, CO, BX, RPT, NT, WPE>), grid, dim3(BX), 0, s,
+                       (const T *)src, (T *)dst, a);
     return hipGetLastError();
 }
 
@@ -788,25 +849,22 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
     }
     if constexpr (CO == CO_MINXENT4) {
         switch (v) {
-        case 3: return go9<ST, CO, 128, 2, 1>(src, dst, a, swz, s);
-        case 4: return go9<ST, CO, 256, 1, 2>(src, dst, a, swz, s);
-        case 5: return go9<ST, CO, 64, 4, 2>(src, dst, a, swz, s);
-        case 6: return go9<ST, CO, 64, 2, 1>(src, dst, a, swz, s);
-        case 7: return go9<ST, CO, 128, 1, 1>(src, dst, a, swz, s);
-        case 8: return go9pf<ST, CO, 256, 2>(src, dst, a, swz, s);
-        case 9: return go9pf<ST, CO, 128, 4>(src, dst, a, swz, s);
-        case 10: return go9pf<ST, CO, 256, 4>(src, dst, a, swz, s);
-        case 11: return go9pf<ST, CO, 64, 8>(src, dst, a, swz, s);
-        case 12: return go9<ST, CO, 256, 1, 1, 1>(src, dst, a, swz, s);
-        case 13: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
-        case 14: return go9pf<ST, CO, 256, 2, 1>(src, dst, a, swz, s);
-        case 15: return go9<ST, CO, 64, 4, 2, 1>(src, dst, a, swz, s);
-        case 16: return go9<ST, CO, 256, 1, 1, 2>(src, dst, a, swz, s);
-        case 17: return go9<ST, CO, 256, 1, 2, 3>(src, dst, a, swz, s);
-        case 18: return go9<ST, CO, 64, 4, 2, 3>(src, dst, a, swz, s);
-        case 19: return go9pf<ST, CO, 256, 4, 3>(src, dst, a, swz, s);
-        case 20: return go9pf<ST, CO, 128, 4, 2>(src, dst, a, swz, s);
-        case 21: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
+        case 3: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
+        case 4: return go9<ST, CO, 256, 1, 1, 2>(src, dst, a, swz, s);
+        case 5: return go9<ST, CO, 256, 1, 1, 3>(src, dst, a, swz, s);
+        case 6: return go9pf<ST, CO, 256, 4, 3>(src, dst, a, swz, s);
+        case 7: return go9<ST, CO, 64, 4, 2, 3>(src, dst, a, swz, s);
+        case 8: return go9pf<ST, CO, 256, 2, 1>(src, dst, a, swz, s);
+        case 9: return go9pf<ST, CO, 128, 4, 2>(src, dst, a, swz, s);
+        case 10: return go9<ST, CO, 256, 1, 2, 3>(src, dst, a, swz, s);
+        case 11: return go9<ST, CO, 256, 1, 1, 3, 6>(src, dst, a, swz, s);
+        case 12: return go9<ST, CO, 256, 1, 1, 3, 8>(src, dst, a, swz, s);
+        case 13: return go9<ST, CO, 256, 1, 1, 2, 6>(src, dst, a, swz, s);
+        case 14: return go9<ST, CO, 256, 1, 1, 3, 6>(src, dst, a, swz, s);
+        case 15: return go9<ST, CO, 256, 1, 1, 3, 7>(src, dst, a, swz, s);
+        case 16: return go9<ST, CO, 256, 1, 1, 1>(src, dst, a, swz, s);
+        case 17: return go9<ST, CO, 128, 1, 1, 3>(src, dst, a, swz, s);
+        case 18: return go9<ST, CO, 512, 1, 1, 3>(src, dst, a, swz, s);
         default: break;
         }
     }

@@ -152,6 +152,48 @@ def test_launch_shapes_are_bitwise_identical(precision):
             assert np.array_equal(g["f"], ref), v
 
 
+def test_launch_shapes_interior_tiles_are_bitwise_identical():
+    # 700 columns: three tiles of 256, so the middle tile takes the interior
+    # neighbour offsets while the two edge tiles apply the wall rule.
+    nx, ny = 700, 70
+    rho, ux, uy = smooth_fields(nx, ny, seed=21)
+    b = B()
+    ctx = b.lbm_init(b.make_params("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.6, 0.0, 0.1, 1.0),
+                     rho, ux, uy)
+    nv = b.lbm_variant_count(ctx)
+    b.lbm_free(ctx)
+    ref = None
+    for v in range(nv):
+        g = gpu_run("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.6, rho, ux, uy, steps=7, u_lid=0.1,
+                    variant=v, want_f=True)
+        ref = g["f"] if ref is None else ref
+        assert np.array_equal(g["f"], ref), v
+
+
+def test_tall_lattice_one_dimensional_grid_matches_oracle():
+    # 70001 rows: one-row tiles exceed the grid's y limit, so those launch
+    # shapes fall back to a one-dimensional grid of tiles.
+    nx, ny = 6, 70001
+    rho, ux, uy = smooth_fields(nx, ny, seed=22)
+    b = B()
+    ctx = b.lbm_init(b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.05, 1.0),
+                     rho, ux, uy)
+    nv = b.lbm_variant_count(ctx)
+    b.lbm_free(ctx)
+    ref = None
+    for v in range(nv):
+        g = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, rho, ux, uy, steps=3, u_lid=0.05,
+                    variant=v, want_f=True)
+        if ref is None:
+            ref = g
+        else:
+            assert np.array_equal(g["f"], ref["f"]), v
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=3, u_lid=0.05)
+    m = fluid_mask("d2q9", "cavity", nx, ny)
+    e = field_errors(ref, o, m)
+    assert all(v[0] <= 1e-12 for v in e.values()), e
+
+
 def test_d1q3_launch_shapes_are_bitwise_identical():
     nx = 5000
     rho, ux = I.tube_fields(nx, 2.0, 0.75)
