@@ -115,7 +115,8 @@ def tubes():
 def test_shock_tube_oscillation_ranking(tubes):
     tv = {c: E().total_variation(t["rho"]) for c, t in tubes.items()}
     print(tv, flush=True)
-    # Two density jumps of 0.5 each (periodic tube): a monotone profile has TV 1.
+    # The initial profile has two jumps of 0.5 (one across the periodic wrap),
+    # so a profile that does not oscillate has TV at most 1.
     assert tv["minxent4"] <= 1.0 + 1e-6 and tv["minxent2"] <= 1.0 + 1e-6
     assert tv["srt"] > 10 * tv["minxent4"] and tv["trt"] > 10 * tv["minxent4"]
     assert tv["mrt"] < tv["srt"]
