@@ -43,6 +43,11 @@ struct W9 {
     static constexpr C diag = C(1.0 / 36.0);
 };
 
+// Fused multiply-add in the compute precision (the double builtin would
+// widen float operands and round twice).
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 __device__ __forceinline__ double rcp(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -138,8 +143,21 @@ __device__ __forceinline__ void ln1p4(const double (&t)[4], double (&out)[4])
     }
 }
 
+// Single precision.  When every |t| < 2^-8 (chosen per wave): the series
+// t - t^2/2 + t^3/3, whose first omitted term is below 2^-24 |t| / 4 (three
+// operations instead of a quarter-rate hardware logarithm and its range
+// handling).  Otherwise logf(1 + t): t = y - 1 is exact for y in [1/2, 2],
+// so 1 + t gives y back (outside that range one more rounding).
 __device__ __forceinline__ void ln1p4(const float (&t)[4], float (&out)[4])
 {
+    const float mt = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(t[0]), __builtin_fabsf(t[1])),
+                                     __builtin_fmaxf(__builtin_fabsf(t[2]), __builtin_fabsf(t[3])));
+    if (mt < 0.00390625f) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[i] = __builtin_fmaf(t[i] * t[i], __builtin_fmaf(t[i], 1.0f / 3.0f, -0.5f), t[i]);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) out[i] = logf(1.0f + t[i]);
 }
@@ -321,10 +339,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     const C wa45 = C(0.5) * rho, wd45 = C(0.125) * rho;
     const C wab = wa * b1, wdb = wd * b1;
     const C s = ux + uy, d = ux - uy;
-    const C ex = __builtin_fma(wa45, uxx, wab) + q8;
-    const C ey = __builtin_fma(wa45, uyy, wab) - q8;
-    const C es = __builtin_fma(wd45, s * s, wdb) + q9;
-    const C ed = __builtin_fma(wd45, d * d, wdb) - q9;
+    const C ex = fma_c(wa45, uxx, wab) + q8;
+    const C ey = fma_c(wa45, uyy, wab) - q8;
+    const C es = fma_c(wd45, s * s, wdb) + q9;
+    const C ed = fma_c(wd45, d * d, wdb) - q9;
     C f0[9];
     f0[0] = (W9<C>::rest * rho) * b1;
     if constexpr (MX2) {
@@ -334,23 +352,23 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         const C m7 = C(2) * (f[4] - f[2]) + (f[5] + f[6]) - (f[7] + f[8]);
         const C q5 = k2 * (m5 + jx) * C(1.0 / 12.0);
         const C q7 = k2 * (m7 + jy) * C(1.0 / 12.0);
-        f0[1] = __builtin_fma(wa3, ux, ex - C(2) * q5);
-        f0[2] = __builtin_fma(wa3, uy, ey - C(2) * q7);
-        f0[3] = __builtin_fma(-wa3, ux, ex + C(2) * q5);
-        f0[4] = __builtin_fma(-wa3, uy, ey + C(2) * q7);
-        f0[5] = __builtin_fma(wd3, s, es + (q5 + q7));
-        f0[6] = __builtin_fma(-wd3, d, ed - (q5 - q7));
-        f0[7] = __builtin_fma(-wd3, s, es - (q5 + q7));
-        f0[8] = __builtin_fma(wd3, d, ed + (q5 - q7));
+        f0[1] = fma_c(wa3, ux, ex - C(2) * q5);
+        f0[2] = fma_c(wa3, uy, ey - C(2) * q7);
+        f0[3] = fma_c(-wa3, ux, ex + C(2) * q5);
+        f0[4] = fma_c(-wa3, uy, ey + C(2) * q7);
+        f0[5] = fma_c(wd3, s, es + (q5 + q7));
+        f0[6] = fma_c(-wd3, d, ed - (q5 - q7));
+        f0[7] = fma_c(-wd3, s, es - (q5 + q7));
+        f0[8] = fma_c(wd3, d, ed + (q5 - q7));
     } else {
-        f0[1] = __builtin_fma(wa3, ux, ex);
-        f0[2] = __builtin_fma(wa3, uy, ey);
-        f0[3] = __builtin_fma(-wa3, ux, ex);
-        f0[4] = __builtin_fma(-wa3, uy, ey);
-        f0[5] = __builtin_fma(wd3, s, es);
-        f0[6] = __builtin_fma(-wd3, d, ed);
-        f0[7] = __builtin_fma(-wd3, s, es);
-        f0[8] = __builtin_fma(wd3, d, ed);
+        f0[1] = fma_c(wa3, ux, ex);
+        f0[2] = fma_c(wa3, uy, ey);
+        f0[3] = fma_c(-wa3, ux, ex);
+        f0[4] = fma_c(-wa3, uy, ey);
+        f0[5] = fma_c(wd3, s, es);
+        f0[6] = fma_c(-wd3, d, ed);
+        f0[7] = fma_c(-wd3, s, es);
+        f0[8] = fma_c(wd3, d, ed);
     }
 
     // Reciprocals r_a = 1/f0_a and the guard: every start population must be
@@ -403,10 +421,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         const double b0 = f0[0] * f0[0];
         const double t31 = f0[3] * r[1], t42 = f0[4] * r[2];
         // y_i - 1 with the last product fused (one rounding).
-        y[0] = __builtin_fma(FR * F, a2 * a2, -1.0);
-        y[1] = __builtin_fma(FR * R, b0 * b0, -1.0);
-        y[2] = __builtin_fma(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), -1.0);
-        y[3] = __builtin_fma(t42 * t42, p1 * (r[7] * r[8]), -1.0);
+        y[0] = fma_c(FR * F, a2 * a2, -1.0);
+        y[1] = fma_c(FR * R, b0 * b0, -1.0);
+        y[2] = fma_c(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), -1.0);
+        y[3] = fma_c(t42 * t42, p1 * (r[7] * r[8]), -1.0);
     } else {
         C sum = f0[0];
 #pragma unroll

@@ -330,8 +330,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
 // Tile (tx, ty) of this block.  The grid is (tiles_x, tiles_y), or one
 // dimension of tiles_x * tiles_y blocks when tiles_y exceeds the grid's y
 // limit.  In dispatch order (x fastest) the hardware deals blocks
-// round-robin to the eight XCDs; with the swizzle the linear block index is
-// remapped so that each XCD works on a contiguous band of rows.
+// round-robin to the eight XCDs, each with its own L2; with the swizzle the
+// linear block index is remapped so that each XCD works on a contiguous band
+// of rows.
 __device__ __forceinline__ void tile_of_block(int swizzle, int tiles_x, int &tx, int &ty)
 {
     if (!swizzle && (int)gridDim.x == tiles_x) {

@@ -601,31 +601,22 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
     const int nv = variant_count(c);
     // Enough launches per shape to time at least ~2e8 node updates.
     const int reps = (int)std::max<int64_t>(3, std::min<int64_t>(50, 200000000 / std::max<int64_t>(1, c->nodes)));
-    float best = 1e30f;
-    int best_v = 0;
-    for (int v = 0; v < nv; ++v) {
+    // Time `n` launches of shape v (the source buffer is the current state
+    // and is never written: the persistent shape runs an odd number of
+    // steps, ending in the other buffer); best of `trials`, in ms per `reps`
+    // launches.
+    auto time_shape = [&](int v, int n, int trials, float &out) -> int {
         int rc = lbm_set_variant(c, v);
         if (rc) return rc;
-        // Source buffer is the current state and is never written here (the
-        // persistent shape runs an odd number of steps, ending in the other
-        // buffer).
         const bool pers = c->batch && v == c->lds_variant;
-        const int preps = reps | 1;
-        for (int r = 0; r < 3; ++r) {
-            if (pers) {
-                HIPCHK(launch_lds(c, c->d_status_scratch, 0, 1, 1));
-            } else {
-                lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
-                HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
-            }
-        }
-        float shape_best = 1e30f;
-        for (int trial = 0; trial < 3; ++trial) {
+        const int pn = n | 1;
+        float best_t = 1e30f;
+        for (int trial = 0; trial < trials; ++trial) {
             HIPCHK(hipEventRecord(e0, c->stream));
             if (pers) {
-                HIPCHK(launch_lds(c, c->d_status_scratch, 0, preps, 1));
+                HIPCHK(launch_lds(c, c->d_status_scratch, 0, pn, 1));
             } else {
-                for (int r = 0; r < reps; ++r) {
+                for (int r = 0; r < n; ++r) {
                     lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
                     HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
                 }
@@ -634,12 +625,40 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (pers) ms = ms * (float)reps / (float)preps;
-            shape_best = std::min(shape_best, ms);
+            ms *= (float)reps / (float)(pers ? pn : n);
+            best_t = std::min(best_t, ms);
         }
-        if (shape_best < best) {
-            best = shape_best;
-            best_v = v;
+        out = best_t;
+        return LBM_OK;
+    };
+    // Stage 1: every shape, a short warm-up then the best of three trials.
+    std::vector<std::pair<float, int>> t1;
+    for (int v = 0; v < nv; ++v) {
+        float ms = 0.0f;
+        int rc = time_shape(v, 3, 1, ms);
+        if (rc == LBM_OK) rc = time_shape(v, reps, 3, ms);
+        if (rc) return rc;
+        t1.emplace_back(ms, v);
+    }
+    std::sort(t1.begin(), t1.end());
+    // Stage 2: the three fastest again with four times longer trials, taken
+    // in turn so that clock drift affects them alike.
+    const int nc = (int)std::min<size_t>(3, t1.size());
+    std::vector<float> t2(nc, 1e30f);
+    for (int round = 0; round < 3; ++round) {
+        for (int k = 0; k < nc; ++k) {
+            float ms = 0.0f;
+            int rc = time_shape(t1[k].second, 4 * reps, 1, ms);
+            if (rc) return rc;
+            t2[k] = std::min(t2[k], ms);
+        }
+    }
+    int best_v = t1[0].second;
+    float best = t2[0];
+    for (int k = 1; k < nc; ++k) {
+        if (t2[k] < best) {
+            best = t2[k];
+            best_v = t1[k].second;
         }
     }
     (void)hipEventDestroy(e0);

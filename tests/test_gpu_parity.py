@@ -152,10 +152,12 @@ def test_launch_shapes_are_bitwise_identical(precision):
             assert np.array_equal(g["f"], ref), v
 
 
-def test_launch_shapes_interior_tiles_are_bitwise_identical():
+@pytest.mark.parametrize("nx,ny", [(700, 70), (2048, 40)])
+def test_launch_shapes_interior_tiles_are_bitwise_identical(nx, ny):
     # 700 columns: three tiles of 256, so the middle tile takes the interior
-    # neighbour offsets while the two edge tiles apply the wall rule.
-    nx, ny = 700, 70
+    # neighbour offsets while the two edge tiles apply the wall rule.  2048
+    # columns: every tile but the first and last of a row is interior, for
+    # every block width.
     rho, ux, uy = smooth_fields(nx, ny, seed=21)
     b = B()
     ctx = b.lbm_init(b.make_params("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.6, 0.0, 0.1, 1.0),
