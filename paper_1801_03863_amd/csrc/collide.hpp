@@ -426,23 +426,29 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         y[2] = fma_c(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), -1.0);
         y[3] = fma_c(t42 * t42, p1 * (r[7] * r[8]), -1.0);
     } else {
-        C sum = f0[0];
+        // Guard on the raw bits, as unsigned integers: a negative value (or
+        // -0), +inf or NaN is at least 0x7f800000, and +0 is 0.
+        uint32_t hi = 0u, lo = 0xffffffffu;
 #pragma unroll
-        for (int a = 1; a < 9; ++a) sum += f0[a];
-        C mn = f0[0];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) mn = __builtin_fmin(mn, f0[a]);
-        ok = mn > C(0) && sum < C(__builtin_huge_valf());
+        for (int a = 0; a < 9; ++a) {
+            const uint32_t u = __builtin_bit_cast(uint32_t, f0[a]);
+            hi = hi > u ? hi : u;
+            lo = lo < u ? lo : u;
+        }
+        ok = hi < 0x7f800000u && lo != 0u;
 #pragma unroll
         for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
-        const C X = ((f0[5] * r[1]) * (f0[6] * r[2])) * ((f0[7] * r[3]) * (f0[8] * r[4]));
-        const C Pe = ((f0[5] * r[0]) * (f0[6] * r[0])) * ((f0[7] * r[0]) * (f0[8] * r[0]));
-        const C Pp = ((f0[0] * r[1]) * (f0[0] * r[2])) * ((f0[0] * r[3]) * (f0[0] * r[4]));
+        const C p1 = f0[5] * f0[6];
+        const C F = p1 * (f0[7] * f0[8]);
+        const C R = (r[1] * r[2]) * (r[3] * r[4]);
+        const C FR = F * R;
+        const C a0 = r[0] * C(64), a2 = a0 * a0;  // (64 r0)^4 = 2^24 r0^4
+        const C b0 = f0[0] * f0[0];
         const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        y[0] = (Pe * X) * C(16777216.0) - C(1);
-        y[1] = Pp * X - C(1);
-        y[2] = (t31 * t31) * ((f0[5] * r[6]) * (f0[8] * r[7])) - C(1);
-        y[3] = (t42 * t42) * ((f0[5] * r[7]) * (f0[6] * r[8])) - C(1);
+        y[0] = fma_c(FR * F, a2 * a2, C(-1));
+        y[1] = fma_c(FR * R, b0 * b0, C(-1));
+        y[2] = fma_c(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), C(-1));
+        y[3] = fma_c(t42 * t42, p1 * (r[7] * r[8]), C(-1));
     }
     if (!ok) {
 #pragma unroll

@@ -610,6 +610,142 @@ __device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict
     return fl;
 }
 
+// Sixteen bytes of stored populations, moved as one vector access.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+struct Chunk {
+    T e[16 / sizeof(T)];
+};
+
+template <class T, bool NT>
+__device__ __forceinline__ void ld8(const T *p, T (&v)[8])
+{
+    constexpr int per = 16 / sizeof(T);
+#pragma unroll
+    for (int c = 0; c < 8 / per; ++c) {
+        const u32x4 *q = (const u32x4 *)(p + c * per);
+        u32x4 w;
+        if constexpr (NT) w = __builtin_nontemporal_load(q);
+        else w = *q;
+        const Chunk<T> b = __builtin_bit_cast(Chunk<T>, w);
+#pragma unroll
+        for (int e = 0; e < per; ++e) v[c * per + e] = b.e[e];
+    }
+}
+
+template <class T, bool NT>
+__device__ __forceinline__ void st8(T *p, const T (&v)[8])
+{
+    constexpr int per = 16 / sizeof(T);
+#pragma unroll
+    for (int c = 0; c < 8 / per; ++c) {
+        Chunk<T> b;
+#pragma unroll
+        for (int e = 0; e < per; ++e) b.e[e] = v[c * per + e];
+        const u32x4 w = __builtin_bit_cast(u32x4, b);
+        u32x4 *q = (u32x4 *)(p + c * per);
+        if constexpr (NT) __builtin_nontemporal_store(w, q);
+        else *q = w;
+    }
+}
+
+// Eight consecutive nodes x0 .. x0+7 of one D1Q3 lattice (x0 a multiple of 8,
+// x0 < nx; plane bases 64-element aligned, planes padded to 64 elements, so
+// each group is 16-byte aligned and inside its plane).  Every plane moves as
+// 16-byte vectors; the two values shifted in from outside the group (plane 1
+// from the left, plane 2 from the right) take one scalar load each, with the
+// same wrap/clamp rule as the one-node form, so results are bitwise equal to
+// it.  Nodes beyond nx in the last group are computed but neither stored nor
+// counted.  Returns true if a valid node was unstable.
+template <int ST, int NT = 0>
+__device__ __forceinline__ bool step3_group8(const typename Form<ST>::T *__restrict__ s,
+                                             typename Form<ST>::T *__restrict__ d, int64_t P, int x0, int nx,
+                                             int bc, typename Form<ST>::C omega, typename Form<ST>::C rho0,
+                                             const StepArgs &a)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    constexpr bool NL = (NT & 1) != 0, NS = (NT & 2) != 0;
+    T v0[8], v1[8], v2[8];
+    ld8<T, NL>(s + x0, v0);
+    ld8<T, NL>(s + P + x0, v1);
+    ld8<T, NL>(s + 2 * P + x0, v2);
+    const bool wrap = bc == BC_PERIODIC;
+    const int jl = nx - 1 - x0 < 7 ? nx - 1 - x0 : 7;  // last valid node of the group
+    const int xl = x0 + jl;
+    const int xm = x0 > 0 ? x0 - 1 : (wrap ? nx - 1 : 0);
+    const int xp = xl < nx - 1 ? xl + 1 : (wrap ? 0 : nx - 1);
+    const T s1 = ldraw<T, NL>(s + P + xm), s2 = ldraw<T, NL>(s + 2 * P + xp);
+    const C r0 = C(2.0 / 3.0) * rho0, r1 = C(1.0 / 6.0) * rho0;
+    bool bad = false;
+    // Results go back into v0 and v2 in place (node j reads only v0[j] and
+    // v2[j+1], not yet overwritten when walking upwards) but into o1 for
+    // plane 1, whose node j reads v1[j-1].
+    T o1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int x = x0 + j;
+        const T rp = j == 0 ? s1 : v1[j > 0 ? j - 1 : 0];
+        const T rm = j < jl ? v2[j < 7 ? j + 1 : 7] : s2;
+        C f0 = load<ST>(&v0[j], r0, a.fp16_iscale);
+        C fp = load<ST>(&rp, r1, a.fp16_iscale);
+        C fm = load<ST>(&rm, r1, a.fp16_iscale);
+        const int role = (bc != BC_PERIODIC && (x == 0 || x == nx - 1)) ? R_WALL : R_FLUID;
+        const int fl = node3<C>(f0, fp, fm, role, omega);
+        bad = bad || (j <= jl && fl);
+        if constexpr (ST == ST_F16DEV) {
+            v0[j] = T((f0 - r0) * a.fp16_scale);
+            o1[j] = T((fp - r1) * a.fp16_scale);
+            v2[j] = T((fm - r1) * a.fp16_scale);
+        } else {
+            v0[j] = T(f0);
+            o1[j] = T(fp);
+            v2[j] = T(fm);
+        }
+    }
+    if (jl == 7) {
+        st8<T, NS>(d + x0, v0);
+        st8<T, NS>(d + P + x0, o1);
+        st8<T, NS>(d + 2 * P + x0, v2);
+    } else {
+        for (int j = 0; j <= jl; ++j) {
+            d[x0 + j] = v0[j];
+            d[P + x0 + j] = o1[j];
+            d[2 * P + x0 + j] = v2[j];
+        }
+    }
+    return bad;
+}
+
+template <int ST, int BX, int NT = 0>
+__global__ __launch_bounds__(BX) void k_d1q3_v8(const typename Form<ST>::T *__restrict__ src,
+                                                typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    const Inst &in = a.one;
+    const int x0 = (blockIdx.x * BX + (int)threadIdx.x) * 8;
+    bool bad = false;
+    if (x0 < in.nx) bad = step3_group8<ST, NT>(src, dst, in.plane, x0, in.nx, a.bc, C(in.omega), C(in.rho0), a);
+    report(a.status, bad, 0, a.step, a.step_base);
+}
+
+template <int ST, int BLK, int NT = 0>
+__global__ __launch_bounds__(BLK) void k_d1q3_batch_v8(const typename Form<ST>::T *__restrict__ src,
+                                                       typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    int t = blockIdx.x;
+    if (a.xcd_swizzle) t = xcd_remap(t, gridDim.x);
+    const int i = a.tile_inst[t];
+    const Inst &in = a.inst[i];
+    const int x0 = a.tile_first[t] + (int)threadIdx.x * 8;
+    bool bad = false;
+    if (x0 < in.nx)
+        bad = step3_group8<ST, NT>(src + in.offset, dst + in.offset, in.plane, x0, in.nx, a.bc, C(in.omega),
+                                   C(in.rho0), a);
+    report(a.status + i, bad, 0, a.step, a.step_base);
+}
+
 template <int ST, int BX, int NPT, int NT = 0>
 __global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restrict__ src,
                                              typename Form<ST>::T *__restrict__ dst, StepArgs a)
@@ -923,8 +1059,21 @@ constexpr Shape3 kShapes3[] = {
     {512, 2, "512 nodes=2"},
     {128, 4, "128 nodes=4"},
     {256, 4, "256 nodes=4 nt-load nt-store"},
+    {256, 8, "256 groups of 8 nodes, 16-byte vectors"},
+    {256, 8, "256 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
+    {128, 8, "128 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
 };
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
+
+template <int ST, int BX, int NT = 0>
+hipError_t go3v(const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int groups = (a.one.nx + 7) / 8;
+    hipLaunchKernelGGL((k_d1q3_v8<ST, BX, NT>), dim3((groups + BX - 1) / BX), dim3(BX), 0, s, (const T *)src,
+                       (T *)dst, a);
+    return hipGetLastError();
+}
 
 template <int ST, int BX, int NPT, int NT = 0>
 hipError_t go3(const void *src, void *dst, const StepArgs &a, hipStream_t s)
@@ -944,6 +1093,9 @@ hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipSt
     case 2: return go3<ST, 512, 2>(src, dst, a, s);
     case 3: return go3<ST, 128, 4>(src, dst, a, s);
     case 4: return go3<ST, 256, 4, 3>(src, dst, a, s);
+    case 5: return go3v<ST, 256>(src, dst, a, s);
+    case 6: return go3v<ST, 256, 3>(src, dst, a, s);
+    case 7: return go3v<ST, 128, 3>(src, dst, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -959,7 +1111,10 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {256, 1, "batch 256 nodes/block nt-store"}};
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
-                                {256, 4, "batch 256x4 nodes/block nt-load nt-store"}};
+                                {256, 4, "batch 256x4 nodes/block nt-load nt-store"},
+                                {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors"},
+                                {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
+                                {128, 8, "batch 128 groups of 8 nodes, 16-byte vectors nt-load nt-store"}};
 
 template <int ST>
 hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
@@ -971,6 +1126,9 @@ hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipS
     case 2: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 4>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 3: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 8>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 4: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 4, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 5: hipLaunchKernelGGL((k_d1q3_batch_v8<ST, 256>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 6: hipLaunchKernelGGL((k_d1q3_batch_v8<ST, 256, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 7: hipLaunchKernelGGL((k_d1q3_batch_v8<ST, 128, 3>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
