@@ -264,8 +264,8 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernel; "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: it measures the fused kernel on one GPU's lattice "
+              "(no multi-GPU path is implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
