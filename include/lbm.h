@@ -100,7 +100,9 @@ typedef struct lbm_status {
     uint32_t flags;      /* bit 0: UNSTABLE, bit 1: GUARDED (some node skipped its Newton step) */
     int32_t reserved;
     int64_t first_step;  /* step (0-based) of the first UNSTABLE event, -1 if none */
-    int64_t guarded;     /* node-steps whose Newton start point had a population <= 0 */
+    int64_t guarded;     /* node-steps that kept their Newton start point: a start population
+                            <= 0 or not finite, or (FP64 arithmetic) a product of the nine
+                            below the smallest normal double */
 } lbm_status_t;
 
 typedef struct lbm_ctx lbm_ctx_t;
@@ -114,7 +116,8 @@ int lbm_workspace_bytes(const lbm_params_t *p, size_t *bytes);
  * given fields (Sec. IV.E, initial state); lid nodes start at the lid
  * equilibrium.  rho, ux, uy: host arrays, nx*ny doubles each (uy ignored and
  * may be NULL for D1Q3); read only during the call.  dev_workspace: caller
- * device memory of ws_bytes >= lbm_workspace_bytes(), or NULL.  On success
+ * device memory of ws_bytes >= lbm_workspace_bytes(), 256-byte aligned
+ * (LBM_EINVAL otherwise), or NULL.  On success
  * *out holds the new context; the device state is ready when the stream
  * reaches this point. */
 int lbm_init(const lbm_params_t *p, const double *rho, const double *ux, const double *uy,
@@ -142,14 +145,19 @@ int lbm_step(lbm_ctx_t *ctx, int64_t nsteps);
 int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
 
 /* Time the candidate launch shapes of the fused kernel on this context's own
- * buffers (the state is left unchanged) and keep the fastest.  Candidates
- * produce bitwise identical results.  If cache_path is not NULL the choice is
- * read from / appended to that text file, keyed by device, lattice,
- * precision, collision, boundary and size.  *chosen (may be NULL) receives
- * the index of the chosen shape. */
+ * buffers (the state is left unchanged) and keep the fastest: every shape
+ * is timed, then the three fastest again with longer trials taken in turn.
+ * Candidates produce bitwise identical results.  If cache_path is not NULL
+ * the choice is read from / appended to that text file, keyed by a hash of
+ * the kernel sources, device, lattice, precision, collision, boundary and
+ * size.  *chosen (may be NULL) receives the index of the chosen shape.
+ * Synchronises.  For a batch, shapes with another tile size rebuild the
+ * tile tables (a device allocation). */
 int lbm_autotune(lbm_ctx_t *ctx, const char *cache_path, int32_t *chosen);
 
-/* Force a launch shape by index (0 = default); LBM_EINVAL if out of range. */
+/* Force a launch shape by index (0 = default); LBM_EINVAL if out of range.
+ * For a batch, a shape with another tile size rebuilds the tile tables (a
+ * device allocation). */
 int lbm_set_variant(lbm_ctx_t *ctx, int32_t variant);
 
 /* Number of launch shapes (for lbm_set_variant) and a short description. */
