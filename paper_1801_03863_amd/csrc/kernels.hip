@@ -397,6 +397,96 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
     report(a.status, bad, guarded, a.step, a.step_base);
 }
 
+// Sixteen bytes of stored populations, moved as one vector access.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// LDS-staged form.  A block of BX threads covers BX columns of RY rows, one
+// row at a time.  For each of the nine planes it stages the source row
+// window [x0 - 1, x0 + BX] that the row's nodes pull from (row shifted by the
+// plane's vertical velocity, columns by at most one) in LDS: the aligned
+// BX-wide middle with 16-byte vector loads when every row start is 16-byte
+// aligned (nx a multiple of the vector width), element by element otherwise,
+// and the two edge columns by single loads.  Window columns outside the
+// lattice hold the wrap/clamp source of the edge nodes, so every node reads
+// exactly what the direct forms read and results are bitwise equal.
+template <int ST, int CO, int BX, int RY, int NT = 0>
+__global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *__restrict__ src,
+                                                   typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    constexpr int V = 16 / sizeof(T);  // elements per vector
+    // LDS row: [V-1] left edge, [V, V+BX) middle (16-byte aligned), [V+BX]
+    // right edge; the row stride is a multiple of 16 bytes.
+    constexpr int W = BX + 2 * V;
+    __shared__ __align__(16) T win[9][W];
+    const Inst &in = a.one;
+    const int nx = in.nx, ny = in.ny;
+    const int64_t P = in.plane;
+    const bool xw = a.bc == BC_PERIODIC;
+    int tx, ty;
+    tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
+    const int t = (int)threadIdx.x;
+    const int x0 = tx * BX;
+    const int x = x0 + t;
+    const bool xin = x < nx;
+    const int xs = xin ? x : nx - 1;
+    const bool vec = (nx % V) == 0;
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+    bool bad = false;
+    int guarded = 0;
+    for (int r = 0; r < RY; ++r) {
+        const int y = ty * RY + r;  // uniform across the block
+        if (y >= ny) break;
+        if (a.bc == BC_CAVITY && y == ny - 1) {
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            continue;
+        }
+        const Nb n = neighbours(0, y, 1, ny, a.bc);  // rows only
+        // Stage the nine windows.
+        for (int i = t; i < 9 * (BX / V); i += BX) {
+            const int q = i / (BX / V), k = i - q * (BX / V);
+            const int vy = cy9(q);
+            const int ys = vy > 0 ? n.ym : (vy < 0 ? n.yp : y);
+            const T *row = src + (int64_t)q * P + (int64_t)ys * nx;
+            const int c0 = x0 + k * V;
+            if (vec && c0 + V <= nx) {
+                const u32x4 *p = (const u32x4 *)(row + c0);
+                u32x4 w;
+                if constexpr ((NT & 1) != 0) w = __builtin_nontemporal_load(p);
+                else w = *p;
+                *(u32x4 *)&win[q][V + k * V] = w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int c = c0 + e;
+                    const int ce = c < nx ? c : ((c == nx && xw) ? 0 : nx - 1);
+                    win[q][V + k * V + e] = ldraw<T, (NT & 1) != 0>(row + ce);
+                }
+            }
+        }
+        if (t < 18) {
+            const int q = t >> 1;
+            const int vy = cy9(q);
+            const int ys = vy > 0 ? n.ym : (vy < 0 ? n.yp : y);
+            const int c = (t & 1) ? x0 + BX : x0 - 1;
+            const int ce = c < 0 ? (xw ? nx - 1 : 0) : (c >= nx ? ((c == nx && xw) ? 0 : nx - 1) : c);
+            win[q][(t & 1) ? V + BX : V - 1] = ldraw<T, (NT & 1) != 0>(src + (int64_t)q * P + (int64_t)ys * nx + ce);
+        }
+        __syncthreads();
+        C f[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = load<ST>(&win[q][t + V - cx9(q)], ref[q], a.fp16_iscale);
+        __syncthreads();  // the windows are restaged for the next row
+        const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
+        bad = bad || (xin && (fl & 1));
+        guarded += __popcll(__ballot(xin && (fl & 2)));
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+    }
+    report(a.status, bad, guarded, a.step, a.step_base);
+}
+
 // Software-pipelined form: a block of BX threads walks RPT consecutive rows;
 // each thread issues the raw loads of its next row before computing the
 // current one, so nine loads per thread are always in flight while the VALU
@@ -611,7 +701,6 @@ __device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict
 }
 
 // Sixteen bytes of stored populations, moved as one vector access.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 struct Chunk {
     T e[16 / sizeof(T)];
@@ -941,6 +1030,7 @@ constexpr Shape kShapes[] = {
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load"},
     {128, 1, 1, 0, "128x1 rows=1 linear nt-load nt-store"},
     {512, 1, 1, 0, "512x1 rows=1 linear nt-load nt-store"},
+    {256, -2, 1, 0, "256 LDS-staged rows=1 linear nt-store"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
@@ -957,6 +1047,19 @@ hipError_t go9(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
     const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
     hipLaunchKernelGGL((k_d2q9<ST, CO, BX, BY, RPT, NT, WPE>), grid, dim3(BX, BY), 0, s,
                        (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST, int CO, int BX, int RY, int NT = 0>
+hipError_t go9st(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int tiles_x = (a.one.nx + BX - 1) / BX;
+    const int tiles_y = (a.one.ny + RY - 1) / RY;
+    a.tiles_x = tiles_x;
+    a.xcd_swizzle = swz;
+    const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
+    hipLaunchKernelGGL((k_d2q9_stage<ST, CO, BX, RY, NT>), grid, dim3(BX), 0, s, (const T *)src, (T *)dst, a);
     return hipGetLastError();
 }
 
@@ -1002,6 +1105,7 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
         case 16: return go9<ST, CO, 256, 1, 1, 1>(src, dst, a, swz, s);
         case 17: return go9<ST, CO, 128, 1, 1, 3>(src, dst, a, swz, s);
         case 18: return go9<ST, CO, 512, 1, 1, 3>(src, dst, a, swz, s);
+        case 19: return go9st<ST, CO, 256, 1, 2>(src, dst, a, swz, s);
         default: break;
         }
     }
