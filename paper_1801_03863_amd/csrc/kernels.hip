@@ -118,27 +118,36 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
 // of x and of its two neighbours.  Row bases are uniform when the rows are
 // (scalar registers), so the loads take the scalar-base + 32-bit
 // vector-offset form.
-template <int ST, bool NT = false>
+// NL selects non-temporal loads: 0 none, 1 every plane, 2 only the three
+// planes without a horizontal shift (rest, N, S), whose cache lines no other
+// tile reads; the six x-shifted planes then keep regular loads, so the line a
+// tile shares with its horizontal neighbour can still be found in cache.
+template <int ST, int NL = 0>
 __device__ __forceinline__ void pull9_cols(const typename Form<ST>::T *__restrict__ s, int64_t P, int y, int ym,
                                            int yp, int nx, uint32_t cc, uint32_t cm, uint32_t cp,
                                            typename Form<ST>::T (&r)[9])
 {
     using T = typename Form<ST>::T;
+    constexpr bool A = NL == 1, U = NL != 0;
     const int64_t PB = P * (int64_t)sizeof(T);
     const int64_t RB = (int64_t)nx * (int64_t)sizeof(T);
     const char *bc_ = (const char *)s + (int64_t)y * RB;
     const char *bm_ = (const char *)s + (int64_t)ym * RB;
     const char *bp_ = (const char *)s + (int64_t)yp * RB;
-    r[0] = ldraw<T, NT>((const T *)(bc_ + cc));
-    r[1] = ldraw<T, NT>((const T *)((bc_ + PB) + cm));
-    r[2] = ldraw<T, NT>((const T *)((bm_ + 2 * PB) + cc));
-    r[3] = ldraw<T, NT>((const T *)((bc_ + 3 * PB) + cp));
-    r[4] = ldraw<T, NT>((const T *)((bp_ + 4 * PB) + cc));
-    r[5] = ldraw<T, NT>((const T *)((bm_ + 5 * PB) + cm));
-    r[6] = ldraw<T, NT>((const T *)((bm_ + 6 * PB) + cp));
-    r[7] = ldraw<T, NT>((const T *)((bp_ + 7 * PB) + cp));
-    r[8] = ldraw<T, NT>((const T *)((bp_ + 8 * PB) + cm));
+    r[0] = ldraw<T, U>((const T *)(bc_ + cc));
+    r[1] = ldraw<T, A>((const T *)((bc_ + PB) + cm));
+    r[2] = ldraw<T, U>((const T *)((bm_ + 2 * PB) + cc));
+    r[3] = ldraw<T, A>((const T *)((bc_ + 3 * PB) + cp));
+    r[4] = ldraw<T, U>((const T *)((bp_ + 4 * PB) + cc));
+    r[5] = ldraw<T, A>((const T *)((bm_ + 5 * PB) + cm));
+    r[6] = ldraw<T, A>((const T *)((bm_ + 6 * PB) + cp));
+    r[7] = ldraw<T, A>((const T *)((bp_ + 7 * PB) + cp));
+    r[8] = ldraw<T, A>((const T *)((bp_ + 8 * PB) + cm));
 }
+
+// Non-temporal load mode of a launch-shape bit mask NT: bit 0 every plane,
+// bit 2 the unshifted planes only (bit 1 is the stores).
+constexpr int nl_mode(int nt) { return (nt & 1) ? 1 : ((nt & 4) ? 2 : 0); }
 
 // Column byte offsets of a node's own column and its two neighbours.  In a
 // tile that touches neither side of the lattice the neighbours are x -+ 1
@@ -168,7 +177,7 @@ __device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict
                                           const Nb &n, typename Form<ST>::T (&r)[9])
 {
     const uint32_t E = sizeof(typename Form<ST>::T);
-    pull9_cols<ST, NT>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
+    pull9_cols<ST, NT ? 1 : 0>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
 }
 
 // Pull and widen the nine populations that stream into node (x, y).
@@ -385,7 +394,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
         C f[9];
         {
             typename Form<ST>::T raw[9];
-            pull9_cols<ST, (NT & 1) != 0>(src, P, y, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+            pull9_cols<ST, nl_mode(NT)>(src, P, y, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
 #pragma unroll
             for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         }
@@ -514,7 +523,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     T raw[9];
     {
         const Nb n = neighbours(0, y0, 1, ny, a.bc);  // rows only
-        pull9_cols<ST, (NT & 1) != 0>(src, P, y0, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+        pull9_cols<ST, nl_mode(NT)>(src, P, y0, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -525,7 +534,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         if (k + 1 < RPT && y + 1 < ny) {
             const Nb n = neighbours(0, y + 1, 1, ny, a.bc);  // rows only
-            pull9_cols<ST, (NT & 1) != 0>(src, P, y + 1, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+            pull9_cols<ST, nl_mode(NT)>(src, P, y + 1, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
         }
         if (a.bc == BC_CAVITY && y == ny - 1) {
             if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
@@ -1031,6 +1040,9 @@ constexpr Shape kShapes[] = {
     {128, 1, 1, 0, "128x1 rows=1 linear nt-load nt-store"},
     {512, 1, 1, 0, "512x1 rows=1 linear nt-load nt-store"},
     {256, -2, 1, 0, "256 LDS-staged rows=1 linear nt-store"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=6"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=8"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
@@ -1106,6 +1118,9 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
         case 17: return go9<ST, CO, 128, 1, 1, 3>(src, dst, a, swz, s);
         case 18: return go9<ST, CO, 512, 1, 1, 3>(src, dst, a, swz, s);
         case 19: return go9st<ST, CO, 256, 1, 2>(src, dst, a, swz, s);
+        case 20: return go9<ST, CO, 256, 1, 1, 6>(src, dst, a, swz, s);
+        case 21: return go9<ST, CO, 256, 1, 1, 6, 6>(src, dst, a, swz, s);
+        case 22: return go9<ST, CO, 256, 1, 1, 6, 8>(src, dst, a, swz, s);
         default: break;
         }
     }
