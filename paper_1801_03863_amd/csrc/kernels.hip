@@ -172,22 +172,23 @@ __device__ __forceinline__ Cols columns(int xs, bool edge_tile, int nx, int bc, 
 }
 
 // Pull the nine raw stored populations that stream into node (x, y).
-template <int ST, bool NT = false>
+template <int ST, int NL = 0>
 __device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
                                           const Nb &n, typename Form<ST>::T (&r)[9])
 {
     const uint32_t E = sizeof(typename Form<ST>::T);
-    pull9_cols<ST, NT ? 1 : 0>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
+    pull9_cols<ST, NL>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
 }
 
-// Pull and widen the nine populations that stream into node (x, y).
-template <int ST, bool NT = false>
+// Pull and widen the nine populations that stream into node (x, y) (NL as
+// for pull9_cols).
+template <int ST, int NL = 0>
 __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
                                       const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
                                       typename Form<ST>::C (&f)[9])
 {
     typename Form<ST>::T r[9];
-    pull9_raw<ST, NT>(s, P, x, y, nx, n, r);
+    pull9_raw<ST, NL>(s, P, x, y, nx, n, r);
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = load<ST>(&r[q], ref[q], iscale);
 }
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     const Nb n = neighbours(x, y, nx, ny, a.bc);
     const typename Form<ST>::T *s = src + in.offset;
     C f[9];
-    pull9<ST, (NT & 1) != 0>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
+    pull9<ST, nl_mode(NT)>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
     const int role = role9(x, y, nx, ny, a.bc);
     const int fl = node9<ST, CO>(f, role, in);
     if (valid) push9<ST, (NT & 2) != 0>(dst + in.offset, P, node, f, ref, a.fp16_scale);
@@ -1150,6 +1151,7 @@ hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a, hipS
     case 1: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 128, 0>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
     case 2: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 3: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 2>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 4: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 6>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1227,7 +1229,8 @@ struct ShapeB {
 };
 constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"},
                                 {256, 1, "batch 256 nodes/block nt-load nt-store"},
-                                {256, 1, "batch 256 nodes/block nt-store"}};
+                                {256, 1, "batch 256 nodes/block nt-store"},
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store"}};
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block nt-load nt-store"},
