@@ -83,3 +83,21 @@ def test_single_lattice_workspace_has_no_batch_size_limit(B):
     assert B.lbm_workspace_bytes(p) == 2 * 9 * 8192 * 8192 * 4
     with pytest.raises(B.LbmError):
         B.lbm_workspace_bytes_batch([p])
+
+
+def test_lattice_size_limit(B):
+    # One instance holds fewer than 2^30 nodes (indices stay within int32 with
+    # room for the nine planes' offsets).
+    big = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 32768, 32768, 0.6)
+    with pytest.raises(B.LbmError) as ei:
+        B.lbm_workspace_bytes(big)
+    assert ei.value.code == B.LBM_EINVAL
+    ok = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 32767, 32768, 0.6)
+    plane = (32767 * 32768 + 63) // 64 * 64
+    assert B.lbm_workspace_bytes(ok) == 2 * ((9 * plane * 2 + 255) // 256 * 256)
+
+
+def test_batch_needs_an_instance(B):
+    with pytest.raises(B.LbmError) as ei:
+        B.lbm_workspace_bytes_batch([])
+    assert ei.value.code == B.LBM_EINVAL

@@ -304,6 +304,33 @@ def test_caller_workspace_and_stream():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(b.LbmError):
         b.lbm_init(p, rho, ux, uy, workspace=small)
+    # A workspace that is not 256-byte aligned is rejected before any device work.
+    big = torch.empty(b.lbm_workspace_bytes(p) + 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(b.LbmError) as ei:
+        b.lbm_init(p, rho, ux, uy, workspace=big[8:])
+    assert ei.value.code == b.LBM_EINVAL
+
+
+def test_argument_errors_leave_the_context_usable():
+    nx, ny = 40, 30
+    rho, ux, uy = smooth_fields(nx, ny, seed=23)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    ctx = b.lbm_init(p, rho, ux, uy)
+    try:
+        nv = b.lbm_variant_count(ctx)
+        for call in (lambda: b.lbm_set_variant(ctx, nv), lambda: b.lbm_set_variant(ctx, -1),
+                     lambda: b.lbm_step(ctx, -1), lambda: b.lbm_set_graph_chunk(ctx, -1)):
+            with pytest.raises(b.LbmError) as ei:
+                call()
+            assert ei.value.code == b.LBM_EINVAL
+        b.lbm_step(ctx, 12)
+        r, u, v = b.lbm_moments(ctx)
+    finally:
+        b.lbm_free(ctx)
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=12, u_lid=0.1)
+    g = {"rho": r.reshape(ny, nx), "ux": u.reshape(ny, nx), "uy": v.reshape(ny, nx)}
+    assert_close(g, o, fluid_mask("d2q9", "cavity", nx, ny), TOL64, label="after errors")
 
 
 def test_copy_kernel():
