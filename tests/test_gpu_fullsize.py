@@ -308,3 +308,79 @@ def test_lds_resident_persistent_batch_is_bitwise(precision, steps):
     for a_, b_ in zip(S1, S2):
         assert a_["unstable"] == b_["unstable"] and a_["first_step"] == b_["first_step"]
         assert a_["guarded"] == b_["guarded"]
+
+
+def test_full_cavity_batch_5000_steps_against_oracle():
+    # The whole 512-cavity batch (22.3 M nodes, sides 32..512, Re 100..10000,
+    # lid 0.1) for its full 5000 steps in FP64; the oracle reruns the four
+    # smallest instances whole.  Instances that blow up are compared by status
+    # and first unstable step.
+    insts = I.cavity_batch(count=512)
+    b = B()
+    params, rs, us, vs = [], [], [], []
+    for i, (n, tau, re) in enumerate(insts):
+        r, u, v = I.cavity_fields(n, 1.0, 1804 * 1000 + i)
+        params.append(b.make_params("d2q9", "minxent4", "cavity", "fp64", n, n, tau, 0.0, 0.1, 1.0))
+        rs.append(r.ravel()); us.append(u.ravel()); vs.append(v.ravel())
+    steps = 5000
+    ctx = b.lbm_init_batch(params, np.concatenate(rs), np.concatenate(us), np.concatenate(vs))
+    try:
+        b.lbm_autotune(ctx)
+        b.lbm_step(ctx, steps)
+        R, U, V = b.lbm_moments(ctx)
+        sts = b.lbm_status_batch(ctx, len(insts))
+    finally:
+        b.lbm_free(ctx)
+    offs = np.concatenate([[0], np.cumsum([n * n for n, _, _ in insts])])
+    pick = sorted(range(len(insts)), key=lambda i: insts[i][0])[:4]
+    for i in pick:
+        n, tau, re = insts[i]
+        o = orc_run("d2q9", "minxent4", "cavity", n, n, tau, rs[i].reshape(n, n), us[i].reshape(n, n),
+                    vs[i].reshape(n, n), steps=steps, u_lid=0.1)
+        assert sts[i]["unstable"] == o["unstable"], (i, n, re)
+        if o["unstable"]:
+            assert sts[i]["first_step"] == o["first_step"], (i, n, re)
+            continue
+        m = n * n
+        g = {"rho": R[offs[i]:offs[i] + m].reshape(n, n), "ux": U[offs[i]:offs[i] + m].reshape(n, n),
+             "uy": V[offs[i]:offs[i] + m].reshape(n, n)}
+        fl = fluid_mask("d2q9", "cavity", n, n)
+        for f in ("rho", "ux", "uy"):
+            err = np.max(np.abs(g[f] - o[f])[fl]) / np.max(np.abs(o[f][fl]))
+            print("cavity", i, n, round(re), f, "%.2e" % err, flush=True)
+            assert err <= 1e-12, (i, n, f, err)
+
+
+def test_full_tube_batch_1000_steps_against_oracle():
+    # The whole 4096-tube batch (62.6 M nodes) for its full 1000 steps in
+    # FP64; the oracle reruns the six shortest tubes whole.
+    tubes = I.tube_batch(count=4096)
+    b = B()
+    params, rs, us = [], [], []
+    for (n, rl, rr, tau) in tubes:
+        r, u = I.tube_fields(n, rl, rr)
+        params.append(b.make_params("d1q3", "srt", "tube", "fp64", n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr)))
+        rs.append(r); us.append(u)
+    steps = 1000
+    ctx = b.lbm_init_batch(params, np.concatenate(rs), np.concatenate(us), None)
+    try:
+        b.lbm_autotune(ctx)
+        b.lbm_step(ctx, steps)
+        R, U, _ = b.lbm_moments(ctx)
+        sts = b.lbm_status_batch(ctx, len(tubes))
+    finally:
+        b.lbm_free(ctx)
+    offs = np.concatenate([[0], np.cumsum([t[0] for t in tubes])])
+    pick = sorted(range(len(tubes)), key=lambda i: tubes[i][0])[:6]
+    for i in pick:
+        n, rl, rr, tau = tubes[i]
+        o = orc_run("d1q3", "srt", "tube", n, 1, tau, rs[i], us[i], steps=steps)
+        assert sts[i]["unstable"] == o["unstable"], (i, n)
+        if o["unstable"]:
+            assert sts[i]["first_step"] == o["first_step"], (i, n)
+            continue
+        fl = fluid_mask("d1q3", "tube", n, 1)
+        er = np.max(np.abs(R[offs[i]:offs[i] + n] - o["rho"])[fl]) / np.max(np.abs(o["rho"][fl]))
+        eu = np.max(np.abs(U[offs[i]:offs[i] + n] - o["ux"])[fl]) / np.max(np.abs(o["ux"][fl]))
+        print("tube", i, n, "rho %.2e u %.2e" % (er, eu), flush=True)
+        assert er <= 1e-12 and eu <= 1e-12, (i, n, er, eu)
