@@ -384,3 +384,34 @@ def test_full_tube_batch_1000_steps_against_oracle():
         eu = np.max(np.abs(U[offs[i]:offs[i] + n] - o["ux"])[fl]) / np.max(np.abs(o["ux"][fl]))
         print("tube", i, n, "rho %.2e u %.2e" % (er, eu), flush=True)
         assert er <= 1e-12 and eu <= 1e-12, (i, n, er, eu)
+
+
+def test_benchmark_cavity_fp64_60_steps_sampled():
+    # The 4096^2 benchmark cavity in FP64 for 60 steps in the autotuned shape;
+    # 12 sampled nodes (corners, lid row, walls, interior) against windowed
+    # oracle runs of (2*61+1)^2 nodes each.
+    c = I.cavity_4096_params()
+    n, steps = c["nx"], 60
+    r, u, v = I.cavity_fields(n, 1.0, c["seed"])
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", n, n, c["tau"], 0.0, c["u_lid"], 1.0)
+    ctx = b.lbm_init(p, r, u, v)
+    try:
+        b.lbm_autotune(ctx)
+        b.lbm_step(ctx, steps)
+        gr, gu, gv = (a.reshape(n, n) for a in b.lbm_moments(ctx))
+        assert not b.lbm_status(ctx)["unstable"]
+    finally:
+        b.lbm_free(ctx)
+    pts = [(1, 1), (n - 2, 1), (1, n - 2), (n - 2, n - 2), (n // 2, n - 2), (n // 3, n - 3), (2 * n // 3, n - 2),
+           (1, n // 2), (n - 2, n // 2), (n // 2, 1), (n // 2, n // 2), (257, n - 5)]
+    worst = {"rho": 0.0, "u": 0.0}
+    umax = 0.0
+    for x, y in pts:
+        o = windowed_oracle(c, n, steps, x, y)
+        worst["rho"] = max(worst["rho"], abs(gr[y, x] - o["rho"]) / abs(o["rho"]))
+        worst["u"] = max(worst["u"], abs(gu[y, x] - o["ux"]), abs(gv[y, x] - o["uy"]))
+        umax = max(umax, abs(o["ux"]), abs(o["uy"]))
+    worst["u"] /= umax
+    print("fp64 60 steps", worst, "umax", umax, flush=True)
+    assert worst["rho"] <= 1e-12 and worst["u"] <= 1e-12
