@@ -11,8 +11,10 @@
 // Layout: structure of arrays, one plane of nx*ny values per direction,
 // x fastest, so every plane read is a unit-stride row shifted by at most one
 // element and every write is aligned and unit-stride.  Populations are read
-// and written exactly once per step; the kernels are bound by HBM bandwidth
-// and by FP64 VALU issue (logarithms and reciprocals of the Newton step).
+// and written exactly once per step.  The kernels are bound by HBM bandwidth
+// in FP64, FP32 and FP32-storage/FP64-compute forms, and by VALU issue (the
+// logarithms, reciprocals and 4 x 4 solve of the Newton step) when the
+// populations are FP16 deviations.
 //
 // Slots of boundary nodes whose upstream node lies outside the lattice read a
 // clamped (in-bounds) location; their values are bounced outward and never
@@ -710,7 +712,8 @@ __device__ __forceinline__ int step3_node(const typename Form<ST>::T *__restrict
     return fl;
 }
 
-// Sixteen bytes of stored populations, moved as one vector access.
+// Sixteen bytes of stored populations viewed as elements, and eight
+// consecutive populations moved as one or more 16-byte vector accesses.
 template <class T>
 struct Chunk {
     T e[16 / sizeof(T)];
