@@ -309,8 +309,13 @@ __device__ __forceinline__ bool any_sign9(const float (&v)[9])
 // the node was guarded: its start point had a population <= 0 or not
 // finite, in which case f holds the start point itself (no Newton step).
 // `stable` is the stability criterion of Sec. IV.G for the result: every
-// population finite and non-negative.
-template <class C, bool MX2>
+// population finite and non-negative.  The nine reciprocals share one
+// hardware reciprocal (Montgomery) in double precision, and in single
+// precision when SHARED_RCP is set: a few ulp less accurate than nine
+// single-precision reciprocals, which is far below the storage error of
+// FP16 deviations (the form that sets it); the product of the nine start
+// values must then also lie in the normal single-precision range.
+template <class C, bool MX2, bool SHARED_RCP = false>
 __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bool &stable)
 {
     // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C), from
@@ -384,23 +389,24 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     C r[9];
     C y[4];  // y_i - 1 for the four products
     bool ok;
-    if constexpr (sizeof(C) == 8) {
+    C p1, F, R;
+    if constexpr (sizeof(C) == 8 || SHARED_RCP) {
         // Montgomery's simultaneous inversion over the order
         // 5 6 7 8 1 2 3 4 0: the prefix product after four factors is F, and
         // the running reciprocal after the first back-substitution step is
         // 1/(F f1 f2 f3 f4), so R = F times it.
-        const double p1 = f0[5] * f0[6];
-        const double p2 = p1 * f0[7];
-        const double F = p2 * f0[8];
-        const double p4 = F * f0[1];
-        const double p5 = p4 * f0[2];
-        const double p6 = p5 * f0[3];
-        const double p7 = p6 * f0[4];
-        const double p8 = p7 * f0[0];
-        double q = rcp(p8);
+        p1 = f0[5] * f0[6];
+        const C p2 = p1 * f0[7];
+        F = p2 * f0[8];
+        const C p4 = F * f0[1];
+        const C p5 = p4 * f0[2];
+        const C p6 = p5 * f0[3];
+        const C p7 = p6 * f0[4];
+        const C p8 = p7 * f0[0];
+        C q = rcp(p8);
         r[0] = q * p7;
         q = q * f0[0];
-        const double R = F * q;
+        R = F * q;
         r[4] = q * p6;
         q = q * f0[4];
         r[3] = q * p5;
@@ -415,16 +421,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         q = q * f0[7];
         r[6] = q * f0[5];
         r[5] = q * f0[6];
-        ok = !any_sign9(f0) && p8 > 2.2250738585072014e-308 && p8 < C(__builtin_huge_val());
-        const double FR = F * R;
-        const double a0 = r[0] * 64.0, a2 = a0 * a0;  // (64 r0)^4 = 2^24 r0^4
-        const double b0 = f0[0] * f0[0];
-        const double t31 = f0[3] * r[1], t42 = f0[4] * r[2];
-        // y_i - 1 with the last product fused (one rounding).
-        y[0] = fma_c(FR * F, a2 * a2, -1.0);
-        y[1] = fma_c(FR * R, b0 * b0, -1.0);
-        y[2] = fma_c(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), -1.0);
-        y[3] = fma_c(t42 * t42, p1 * (r[7] * r[8]), -1.0);
+        if constexpr (sizeof(C) == 8)
+            ok = !any_sign9(f0) && p8 > 2.2250738585072014e-308 && p8 < C(__builtin_huge_val());
+        else
+            ok = !any_sign9(f0) && p8 > 1.17549435e-38f && p8 < C(__builtin_huge_valf());
     } else {
         // Guard on the raw bits, as unsigned integers: a negative value (or
         // -0), +inf or NaN is at least 0x7f800000, and +0 is 0.
@@ -438,13 +438,16 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         ok = hi < 0x7f800000u && lo != 0u;
 #pragma unroll
         for (int a = 0; a < 9; ++a) r[a] = rcp(f0[a]);
-        const C p1 = f0[5] * f0[6];
-        const C F = p1 * (f0[7] * f0[8]);
-        const C R = (r[1] * r[2]) * (r[3] * r[4]);
+        p1 = f0[5] * f0[6];
+        F = p1 * (f0[7] * f0[8]);
+        R = (r[1] * r[2]) * (r[3] * r[4]);
+    }
+    {
         const C FR = F * R;
         const C a0 = r[0] * C(64), a2 = a0 * a0;  // (64 r0)^4 = 2^24 r0^4
         const C b0 = f0[0] * f0[0];
         const C t31 = f0[3] * r[1], t42 = f0[4] * r[2];
+        // y_i - 1 with the last product fused (one rounding).
         y[0] = fma_c(FR * F, a2 * a2, C(-1));
         y[1] = fma_c(FR * R, b0 * b0, C(-1));
         y[2] = fma_c(t31 * t31, (f0[5] * f0[8]) * (r[6] * r[7]), C(-1));
