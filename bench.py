@@ -90,12 +90,15 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
             "fields": {"rho": r, "ux": u, "uy": v}, "status": st}
 
 
-def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None):
-    """Time a batched context (one launch per step over every instance)."""
+def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, graph_chunk=0):
+    """Time a batched context: one launch per step over every instance, replayed
+    from captured HIP graphs of graph_chunk steps when graph_chunk > 0."""
     ws = torch.empty(B.lbm_workspace_bytes_batch(params), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     ctx = B.lbm_init_batch(params, rho, ux, uy, workspace=ws, stream=stream)
     variant = B.lbm_autotune(ctx, tune_cache)
+    if graph_chunk > 0:
+        B.lbm_set_graph_chunk(ctx, graph_chunk)
     B.lbm_step(ctx, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -111,6 +114,8 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None):
     st = B.lbm_status(ctx)
     per = B.lbm_status_batch(ctx, len(params))
     shape = B.lbm_variant_name(ctx, variant)
+    if graph_chunk > 0:
+        shape += ", HIP graphs of %d steps" % graph_chunk
     B.lbm_free(ctx)
     del ws
     return {"wall_s": wall, "event_ms": e0.elapsed_time(e1), "variant": shape, "nodes": info["nodes"],
@@ -138,9 +143,10 @@ def rel_errors(a, b, mask):
     return out
 
 
-def batched_cavities(B, torch, I, steps, warmup, tune_cache=None):
+def batched_cavities(B, torch, I, steps, warmup, tune_cache=None, graph_chunk=0):
     """512 cavities, sides log-uniform in [32, 512], Re uniform in [100, 1e4],
-    lid 0.1, FP32, one launch per step; error against the same batch in FP64."""
+    lid 0.1, FP32, one launch per step (replayed from HIP graphs when
+    graph_chunk > 0); error against the same batch in FP64."""
     import numpy as np
     insts = I.cavity_batch(count=512)
     fields = [I.cavity_fields(n, 1.0, 1804 * 1000 + i) for i, (n, tau, re) in enumerate(insts)]
@@ -156,7 +162,7 @@ def batched_cavities(B, torch, I, steps, warmup, tune_cache=None):
     res = {}
     for prec in ("fp32", "fp64"):
         params = [B.make_params("d2q9", "minxent4", "cavity", prec, n, n, tau, 0.0, 0.1, 1.0) for n, tau, re in insts]
-        res[prec] = time_batch(B, torch, params, rho, ux, ux, steps, warmup, tune_cache)
+        res[prec] = time_batch(B, torch, params, rho, ux, ux, steps, warmup, tune_cache, graph_chunk)
         out[prec] = rate(res[prec], steps)
     out["field_error_fp32_vs_fp64"] = rel_errors(res["fp32"]["fields"], res["fp64"]["fields"], mask)
     out["instances"] = len(insts)
@@ -183,7 +189,7 @@ def fp16_cavity(B, torch, I, steps, warmup, tune_cache):
     return out
 
 
-def fp16_tubes(B, torch, I, steps, warmup, tune_cache=None):
+def fp16_tubes(B, torch, I, steps, warmup, tune_cache=None, graph_chunk=0):
     """4096 D1Q3 shock tubes, lengths log-uniform in [1024, 65536], density
     ratio in [1.5, 4], tau in [0.505, 0.6]: FP16 deviations against FP64.
     On D1Q3 the method is SRT, which breaks down for the sharpest tubes near
@@ -197,7 +203,7 @@ def fp16_tubes(B, torch, I, steps, warmup, tune_cache=None):
     for prec in ("fp16dev", "fp64"):
         params = [B.make_params("d1q3", "srt", "tube", prec, n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr))
                   for n, rl, rr, tau in tubes]
-        res[prec] = time_batch(B, torch, params, rho, ux, None, steps, warmup, tune_cache)
+        res[prec] = time_batch(B, torch, params, rho, ux, None, steps, warmup, tune_cache, graph_chunk)
         out[prec] = rate(res[prec], steps)
         out[prec]["unstable_instances"] = int(sum(s_["unstable"] for s_ in res[prec]["per_instance"]))
     masks = []
@@ -262,6 +268,8 @@ def main():
                     help="autotuner cache (entries are keyed by a hash of the kernel sources)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and FP16 workloads")
     ap.add_argument("--extra-steps", type=int, default=500)
+    ap.add_argument("--batch-graph-chunk", type=int, default=50,
+                    help="steps per captured HIP graph for the batched workloads (0: plain launches)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: it measures the fused kernel on one GPU's lattice "
@@ -322,10 +330,12 @@ def main():
         ref32 = time_form(B, torch, "fp32", n, tau, cfg["u_lid"], fields, args.extra_steps, args.warmup,
                           args.tune_cache)
         out["fp32"] = rate(ref32, args.extra_steps)
-        out["batched_cavities_512"] = batched_cavities(B, torch, I, args.extra_steps, args.warmup, args.tune_cache)
+        out["batched_cavities_512"] = batched_cavities(B, torch, I, args.extra_steps, args.warmup, args.tune_cache,
+                                                       args.batch_graph_chunk)
         out["fp16dev_cavity_8192"] = fp16_cavity(B, torch, I, min(args.extra_steps, 300), args.warmup,
                                                  args.tune_cache)
-        out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup, args.tune_cache)
+        out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup, args.tune_cache,
+                                               args.batch_graph_chunk)
     out["copy_kernel_gbs"] = round(copy_bandwidth(B, torch), 1)
     out["kernel_source_sha256_16"] = digest
     if not args.no_cpu_baseline:

@@ -252,7 +252,7 @@ def test_reduced_precision_forms_long_run_error():
         assert e_rho <= tol_rho and e_u <= tol_u, prec
 
 
-def test_batched_tube_shapes_bitwise():
+def test_batched_tube_shapes_and_graph_bitwise():
     tubes = I.tube_batch(count=4096)[:40]
     b = B()
     params = [b.make_params("d1q3", "srt", "tube", "fp16dev", n, 1, tau, 0.0, 0.0, 0.5 * (rl + rr))
@@ -265,15 +265,20 @@ def test_batched_tube_shapes_bitwise():
     b.lbm_free(ctx)
     assert nv >= 4
     for v in range(nv):
-        ctx = b.lbm_init_batch(params, rho, ux, None)
-        try:
-            b.lbm_set_variant(ctx, v)
-            b.lbm_step(ctx, 30)
-            F = b.lbm_get_populations(ctx, 3)
-        finally:
-            b.lbm_free(ctx)
-        ref = F if ref is None else ref
-        assert np.array_equal(ref, F), v
+        # every launch shape, plain launches and HIP-graph replay (30 steps =
+        # four graphs of 7 steps + 2 plain launches)
+        for graph in (0, 7):
+            ctx = b.lbm_init_batch(params, rho, ux, None)
+            try:
+                b.lbm_set_variant(ctx, v)
+                if graph:
+                    b.lbm_set_graph_chunk(ctx, graph)
+                b.lbm_step(ctx, 30)
+                F = b.lbm_get_populations(ctx, 3)
+            finally:
+                b.lbm_free(ctx)
+            ref = F if ref is None else ref
+            assert np.array_equal(ref, F), (v, graph)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
