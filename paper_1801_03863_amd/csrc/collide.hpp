@@ -68,56 +68,53 @@ __device__ __forceinline__ double rcp1(double x)
 
 __device__ __forceinline__ float rcp1(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// ln(1 + t) of four doubles t > -1 (finite).  Arguments close to zero take
-// short series (below); otherwise argument reduction y = 1 + t = m 2^k with
-// m in [sqrt(1/2), sqrt(2)), then ln m = 2 atanh(s) with s = (m - 1)/(m + 1),
-// |s| <= 0.1716, summed as the odd series through s^19 (truncation below
-// 2^-54), and k ln 2 added with ln 2 split into a 32-bit head and a tail
-// (the Cody-Waite / fdlibm split).  Error <= 2-3 ulp on every path (the
-// general path rounds 1 + t once more).
+// ln(1 + t) = t + t^2 Q(t) by the Taylor series through the t^N term:
+// Q(t) = sum_{k=0}^{N-2} (-1)^(k+1) t^k / (k+2), by Horner's rule (N - 2
+// fused multiply-adds, one product and one final fma).  For |t| < 2^-b the
+// first omitted term is below 2^(-b N) |t| / (N + 1).
+template <int N>
+__device__ __forceinline__ double ln1p_taylor(double x)
+{
+    double q = ((N - 2) % 2 ? 1.0 : -1.0) / N;
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) q = __builtin_fma(q, x, (k % 2 ? 1.0 : -1.0) / (k + 2));
+    return __builtin_fma(x * x, q, x);
+}
+
+// ln(1 + t) of four doubles t > -1 (finite), chosen per value by max |t|
+// over the four:
+//   |t| < 2^-16 (fluid close to rest)      Taylor through t^4  (omitted term < 2^-64 |t| / 5)
+//   |t| < 2^-8  (the bulk of a smooth flow) Taylor through t^7  (< 2^-56 |t| / 8)
+//   |t| < 2^-5  (developed, faster flow)    Taylor through t^11 (< 2^-55 |t| / 12)
+// otherwise argument reduction y = 1 + t = m 2^k with m in [sqrt(1/2),
+// sqrt(2)), then ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716,
+// summed as the odd series through s^19 (truncation below 2^-54), and k ln 2
+// added with ln 2 split into a 32-bit head and a tail (the Cody-Waite /
+// fdlibm split).  Error <= 2-3 ulp on every path (the general path rounds
+// 1 + t once more).
 __device__ __forceinline__ void ln1p4(const double (&t)[4], double (&out)[4])
 {
     const double mt = __builtin_fmax(__builtin_fmax(__builtin_fabs(t[0]), __builtin_fabs(t[1])),
                                      __builtin_fmax(__builtin_fabs(t[2]), __builtin_fabs(t[3])));
+    if (mt < 1.52587890625e-05) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<4>(t[i]);
+        return;
+    }
     if (mt < 0.00390625) {
-        // Nearest tier, |t| < 2^-8 (the bulk of a smooth flow): the Taylor
-        // series ln(1 + t) = t + t^2 Q(t) with Q through the t^7 term; the
-        // first omitted term is below 2^-56 |t| / 8.
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double x = t[i];
-            double q = 1.0 / 7.0;
-            q = __builtin_fma(q, x, -1.0 / 6.0);
-            q = __builtin_fma(q, x, 1.0 / 5.0);
-            q = __builtin_fma(q, x, -0.25);
-            q = __builtin_fma(q, x, 1.0 / 3.0);
-            q = __builtin_fma(q, x, -0.5);
-            out[i] = __builtin_fma(x * x, q, x);
-        }
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<7>(t[i]);
         return;
     }
-    // The two remaining tiers are rare (steep gradients); they take one
-    // reciprocal per value rather than a shared one, which keeps few values
-    // live: the register budget of the whole kernel is set by its busiest
-    // point, and these paths must not be it.
-    if (mt < 0.0625) {
-        // Near tier, |t| < 1/16: s = t/(2 + t) has |s| <= 0.0323 and the
-        // atanh series through s^11 is below 2^-60.
+    if (mt < 0.03125) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double s = t[i] * rcp(2.0 + t[i]);
-            const double z = s * s;
-            double p = 1.0 / 13.0;
-            p = __builtin_fma(p, z, 1.0 / 11.0);
-            p = __builtin_fma(p, z, 1.0 / 9.0);
-            p = __builtin_fma(p, z, 1.0 / 7.0);
-            p = __builtin_fma(p, z, 1.0 / 5.0);
-            p = __builtin_fma(p, z, 1.0 / 3.0);
-            const double tt = s + s;
-            out[i] = __builtin_fma(tt * z, p, tt);
-        }
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<11>(t[i]);
         return;
     }
+    // The general path is rare (steep gradients); it takes one reciprocal
+    // per value rather than a shared one, which keeps few values live: the
+    // register budget of the whole kernel is set by its busiest point, and
+    // this path must not be it.
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const double y = 1.0 + t[i];

@@ -148,7 +148,9 @@ __device__ __forceinline__ void pull9_cols(const typename Form<ST>::T *__restric
 }
 
 // Non-temporal load mode of a launch-shape bit mask NT: bit 0 every plane,
-// bit 2 the unshifted planes only (bit 1 is the stores).
+// bit 2 the unshifted planes only (bit 1 is the stores; bit 3, in the
+// single-lattice D2Q9 kernel, raises the wave's issue priority while it
+// issues its loads).
 constexpr int nl_mode(int nt) { return (nt & 1) ? 1 : ((nt & 4) ? 2 : 0); }
 
 // Column byte offsets of a node's own column and its two neighbours.  In a
@@ -370,6 +372,10 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(WPE > 0 
 void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
     using C = typename Form<ST>::C;
+    // NT bit 3: the wave runs at raised issue priority until its loads are
+    // in flight, so a new wave gets its memory requests out ahead of the
+    // arithmetic of older waves.
+    if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(2);
     const Inst &in = a.one;
     const int nx = in.nx, ny = in.ny;
     const int64_t P = in.plane;
@@ -398,6 +404,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
         {
             typename Form<ST>::T raw[9];
             pull9_cols<ST, nl_mode(NT)>(src, P, y, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+            if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         }
@@ -1047,6 +1054,9 @@ constexpr Shape kShapes[] = {
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=6"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=8"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store prio"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=6 prio"},
+    {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=8 prio"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
@@ -1125,6 +1135,9 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
         case 20: return go9<ST, CO, 256, 1, 1, 6>(src, dst, a, swz, s);
         case 21: return go9<ST, CO, 256, 1, 1, 6, 6>(src, dst, a, swz, s);
         case 22: return go9<ST, CO, 256, 1, 1, 6, 8>(src, dst, a, swz, s);
+        case 23: return go9<ST, CO, 256, 1, 1, 14>(src, dst, a, swz, s);
+        case 24: return go9<ST, CO, 256, 1, 1, 14, 6>(src, dst, a, swz, s);
+        case 25: return go9<ST, CO, 256, 1, 1, 14, 8>(src, dst, a, swz, s);
         default: break;
         }
     }

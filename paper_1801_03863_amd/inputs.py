@@ -67,6 +67,22 @@ def cavity_fields_window(n: int, x0: int, y0: int, wx: int, wy: int, rho0: float
     return rho, z, z.copy()
 
 
+def vortex_fields(n: int, u_max: float, rho0: float = 1.0):
+    """A lattice-filling vortex with zero velocity on the walls: stream
+    function psi = -A sin^2(pi x/L) sin^2(pi y/L), L = n - 1, u_x = d psi/dy,
+    u_y = -d psi/dx, with A set so that max |u| is about u_max; rho = rho0.
+    A flow that moves everywhere (the cavity benchmark itself starts at
+    rest)."""
+    L = n - 1.0
+    x = np.arange(n, dtype=np.float64)
+    sx, s2x = np.sin(np.pi * x / L) ** 2, np.sin(2.0 * np.pi * x / L)
+    # max over the lattice of |d/dy sin^2(pi y/L)| = pi/L at y = L/4
+    amp = u_max * L / np.pi
+    ux = -amp * (np.pi / L) * np.outer(s2x, sx)    # [y, x]: sin^2 in x, sin(2 .) in y
+    uy = amp * (np.pi / L) * np.outer(sx, s2x)
+    return np.full((n, n), rho0), ux, uy
+
+
 def tube_fields(n: int, rho_left: float, rho_right: float, split: int | None = None):
     """Density step: rho_left for x < split, rho_right for x >= split; u = 0."""
     split = n // 2 if split is None else split
