@@ -72,7 +72,9 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_TUBE = 1, LBM_BC_CAVITY = 2, LBM_BC_BOX = 3 }
 /* Storage / arithmetic forms.
  *   FP64:          populations stored and computed in double.
  *   FP32_NEWTON64: populations stored in float, every node computed in
- *                  double (moments, logarithms, Newton step, correction).
+ *                  double (moments, logarithms, Newton step, correction);
+ *                  reciprocal refinements and log series stop about 2^-42
+ *                  relative, four orders below the float storage rounding.
  *   FP32:          stored and computed in float (the four logarithms of the
  *                  gradient are taken of products of population ratios that
  *                  are each close to one).

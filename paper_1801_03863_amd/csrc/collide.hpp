@@ -140,6 +140,36 @@ __device__ __forceinline__ void ln1p4(const double (&t)[4], double (&out)[4])
     }
 }
 
+// The same for a form whose populations are stored in single precision:
+// the series stop once the first omitted term is below 2^-42 |t|, four
+// orders of magnitude under the storage rounding (2^-24), so each tier is
+// shorter:
+//   |t| < 2^-14  through t^3  (omitted term < 2^-42 |t| / 4)
+//   |t| < 2^-8   through t^5  (< 2^-40 |t| / 6)
+//   |t| < 2^-5   through t^8  (< 2^-40 |t| / 9)
+// and the general path is the full-precision one.
+__device__ __forceinline__ void ln1p4_lean(const double (&t)[4], double (&out)[4])
+{
+    const double mt = __builtin_fmax(__builtin_fmax(__builtin_fabs(t[0]), __builtin_fabs(t[1])),
+                                     __builtin_fmax(__builtin_fabs(t[2]), __builtin_fabs(t[3])));
+    if (mt < 6.103515625e-05) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<3>(t[i]);
+        return;
+    }
+    if (mt < 0.00390625) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<5>(t[i]);
+        return;
+    }
+    if (mt < 0.03125) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = ln1p_taylor<8>(t[i]);
+        return;
+    }
+    ln1p4(t, out);
+}
+
 // Single precision.  When every |t| < 2^-8 (chosen per wave): the series
 // t - t^2/2 + t^3/3, whose first omitted term is below 2^-24 |t| / 4 (three
 // operations instead of a quarter-rate hardware logarithm and its range
@@ -201,18 +231,31 @@ struct Sym4 {
     C ee, ep, pp, ex, px, xx, ey, py, xy, yy;
 };
 
-template <class C>
+// Pivot reciprocal: one Newton step on the hardware estimate, or the
+// estimate alone where LEAN (single-precision storage: the solve's relative
+// error, a few times 1e-7, scales a correction that is itself small next to
+// the populations, so it stays far below their storage rounding).
+template <bool LEAN, class C>
+__device__ __forceinline__ C pivot_rcp(C x)
+{
+    if constexpr (LEAN && sizeof(C) == 8)
+        return __builtin_amdgcn_rcp(x);
+    else
+        return rcp1(x);
+}
+
+template <class C, bool LEAN = false>
 __device__ __forceinline__ void ldlt_solve4(const Sym4<C> &h, C (&g)[4])
 {
-    const C d0 = h.ee, i0 = rcp1(d0);
+    const C d0 = h.ee, i0 = pivot_rcp<LEAN>(d0);
     const C l10 = h.ep * i0, l20 = h.ex * i0, l30 = h.ey * i0;
-    const C d1 = h.pp - l10 * h.ep, i1 = rcp1(d1);
+    const C d1 = h.pp - l10 * h.ep, i1 = pivot_rcp<LEAN>(d1);
     const C t21 = h.px - l20 * h.ep, t31 = h.py - l30 * h.ep;
     const C l21 = t21 * i1, l31 = t31 * i1;
-    const C d2 = h.xx - l20 * h.ex - l21 * t21, i2 = rcp1(d2);
+    const C d2 = h.xx - l20 * h.ex - l21 * t21, i2 = pivot_rcp<LEAN>(d2);
     const C t32 = h.xy - l30 * h.ex - l31 * t21;
     const C l32 = t32 * i2;
-    const C d3 = h.yy - l30 * h.ey - l31 * t31 - l32 * t32, i3 = rcp1(d3);
+    const C d3 = h.yy - l30 * h.ey - l31 * t31 - l32 * t32, i3 = pivot_rcp<LEAN>(d3);
     // forward (unit lower), diagonal, backward
     const C z0 = g[0];
     const C z1 = g[1] - l10 * z0;
@@ -311,10 +354,16 @@ __device__ __forceinline__ bool any_sign9(const float (&v)[9])
 // precision when SHARED_RCP is set: a few ulp less accurate than nine
 // single-precision reciprocals, which is far below the storage error of
 // FP16 deviations (the form that sets it); the product of the nine start
-// values must then also lie in the normal single-precision range.
-template <class C, bool MX2, bool SHARED_RCP = false>
+// values must then also lie in the normal single-precision range.  LEAN (a
+// double-precision step for populations stored in single precision) keeps
+// the arithmetic in double but stops each refinement once it is four orders
+// of magnitude below the storage rounding: one Newton step on the
+// reciprocals of rho and of the product (about 1e-15), none on the four
+// pivots of the solve, and the shorter log series of ln1p4_lean.
+template <class C, bool MX2, bool SHARED_RCP = false, bool LEAN = false>
 __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bool &stable)
 {
+    constexpr bool lean = LEAN && sizeof(C) == 8;
     // Moments of the pre-collision populations (Sec. II.A, Sec. IV.C), from
     // shared pair sums and differences.
     const C a13 = f[1] + f[3], a24 = f[2] + f[4], m13 = f[1] - f[3], m24 = f[2] - f[4];
@@ -324,7 +373,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     const C jy = m24 + (n57 + n68);
     const C pxxyy = a13 - a24;  // sum f (vx^2 - vy^2)
     const C pxy = d57 - d68;    // sum f vx vy
-    const C irho = rcp(rho);
+    const C irho = lean ? rcp1(rho) : rcp(rho);
     const C ux = jx * irho, uy = jy * irho;
     // Relaxed stress constraints C8, C9 as deviations from equilibrium.
     const C k = C(1) - omega;
@@ -400,7 +449,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         const C p6 = p5 * f0[3];
         const C p7 = p6 * f0[4];
         const C p8 = p7 * f0[0];
-        C q = rcp(p8);
+        C q = lean ? rcp1(p8) : rcp(p8);
         r[0] = q * p7;
         q = q * f0[0];
         R = F * q;
@@ -463,7 +512,10 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         return true;
     }
     C g[4];
-    ln1p4(y, g);
+    if constexpr (lean)
+        ln1p4_lean(y, g);
+    else
+        ln1p4(y, g);
 
     // Hessian H = A^T diag(r) A, from pair sums and differences of the r.
     const C r13 = r[1] + r[3], r24 = r[2] + r[4], s13 = r[1] - r[3], s24 = r[2] - r[4];
@@ -492,7 +544,7 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
         h.xx = C(4) * r13 + Sd;
         h.yy = C(4) * r24 + Sd;
         h.xy = r57 - r68;
-        ldlt_solve4(h, g);
+        ldlt_solve4<C, lean>(h, g);
         de = g[0];
         dp = g[1];
         dx = g[2];

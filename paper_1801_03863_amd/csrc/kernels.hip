@@ -270,7 +270,7 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
     // increments (MinxEnt) or by the sum (the other rules).
     if constexpr (CO == CO_MINXENT4 || CO == CO_MINXENT2) {
         bool ok = true;
-        const bool g = collide_minxent<C, CO == CO_MINXENT2, ST == ST_F16DEV>(f, C(in.omega), C(in.omega2), ok);
+        const bool g = collide_minxent<C, CO == CO_MINXENT2, ST == ST_F16DEV, ST == ST_F32N64>(f, C(in.omega), C(in.omega2), ok);
         return (g ? 2 : 0) | (ok ? 0 : 1);
     } else {
         if constexpr (CO == CO_SRT) {
