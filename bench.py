@@ -83,6 +83,9 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
     r, u, v = B.lbm_moments(ctx)
     st = B.lbm_status(ctx)
     shape = B.lbm_variant_name(ctx, variant)
+    pad = B.lbm_get_layout(ctx)[1]
+    if pad >= 0:
+        shape += ", plane pad %d B" % pad
     B.lbm_free(ctx)
     del ws
     return {"wall_s": wall, "event_ms": ev_ms, "variant": shape,

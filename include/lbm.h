@@ -153,9 +153,27 @@ int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
  * the choice is read from / appended to that text file, keyed by a hash of
  * the kernel sources, device, lattice, precision, collision, boundary and
  * size.  *chosen (may be NULL) receives the index of the chosen shape.
- * Synchronises.  For a batch, shapes with another tile size rebuild the
- * tile tables (a device allocation). */
+ * A single lattice whose planes hold at least 1 MiB also has its plane pad
+ * tuned (see lbm_set_plane_pad) with the chosen shape; the cache line then
+ * carries the pad too.  Synchronises.  For a batch, shapes with another tile
+ * size rebuild the tile tables (a device allocation). */
 int lbm_autotune(lbm_ctx_t *ctx, const char *cache_path, int32_t *chosen);
+
+/* Plane pad of a single lattice whose planes hold at least 1 MiB.  The b
+ * population planes of a buffer follow each other at a stride of
+ * round_up(nodes, 64) elements plus pad_bytes; the workspace is sized for the
+ * largest pad (8192 bytes), and contexts start at 2048.  A stride that is a
+ * large power of two starts all planes at the same memory-channel offset, and
+ * which pad avoids that best depends on the size, so the autotuner measures
+ * it.  pad_bytes: a multiple of 256 in [0, 8192].  The state moves to the
+ * new layout (the other buffer becomes current); results are bitwise the
+ * same.  LBM_EINVAL for a batch, a lattice with smaller planes, or a bad pad.
+ * Synchronises. */
+int lbm_set_plane_pad(lbm_ctx_t *ctx, int32_t pad_bytes);
+
+/* Layout of instance 0: the plane stride in elements and the plane pad in
+ * bytes (-1 for a context that takes none); either pointer may be NULL. */
+int lbm_get_layout(const lbm_ctx_t *ctx, int64_t *plane_stride, int32_t *pad_bytes);
 
 /* Force a launch shape by index (0 = default); LBM_EINVAL if out of range.
  * For a batch, a shape with another tile size rebuilds the tile tables (a

@@ -91,6 +91,8 @@ _sig("lbm_autotune", ctypes.c_int, [_V, ctypes.c_char_p, ctypes.POINTER(ctypes.c
 _sig("lbm_set_variant", ctypes.c_int, [_V, ctypes.c_int32])
 _sig("lbm_variant_count", ctypes.c_int, [_V])
 _sig("lbm_variant_name", ctypes.c_char_p, [_V, ctypes.c_int32])
+_sig("lbm_set_plane_pad", ctypes.c_int, [_V, ctypes.c_int32])
+_sig("lbm_get_layout", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)])
 _sig("lbm_moments", ctypes.c_int, [_V, _D, _D, _D])
 _sig("lbm_get_populations", ctypes.c_int, [_V, _D])
 _sig("lbm_set_populations", ctypes.c_int, [_V, _D])
@@ -215,6 +217,17 @@ def lbm_set_variant(ctx, v):
 
 def lbm_variant_count(ctx):
     return _lib.lbm_variant_count(ctx)
+
+
+def lbm_set_plane_pad(ctx, pad_bytes):
+    _check(_lib.lbm_set_plane_pad(ctx, int(pad_bytes)), "lbm_set_plane_pad")
+
+
+def lbm_get_layout(ctx):
+    """(plane stride in elements, plane pad in bytes or -1) of instance 0."""
+    stride, pad = _I64(0), ctypes.c_int32(0)
+    _check(_lib.lbm_get_layout(ctx, ctypes.byref(stride), ctypes.byref(pad)), "lbm_get_layout")
+    return stride.value, pad.value
 
 
 def lbm_variant_name(ctx, v):

@@ -55,13 +55,21 @@ __device__ __forceinline__ T ldraw(const T *p)
     else return *p;
 }
 
+// FP16 deviation of v from ref, scaled by the power of two `scale`: the
+// fused form v*scale - ref*scale rounds once, straight to binary16 (one
+// mixed-precision fma); ref*scale is exact and uniform across the wave.
+__device__ __forceinline__ _Float16 enc16(float v, float ref, float scale)
+{
+    return (_Float16)__builtin_fmaf(v, scale, -(ref * scale));
+}
+
 template <int ST, bool NT = false>
 __device__ __forceinline__ void store(typename Form<ST>::T *p, typename Form<ST>::C v, typename Form<ST>::C ref,
                                       float scale)
 {
     using T = typename Form<ST>::T;
     T t;
-    if constexpr (ST == ST_F16DEV) t = T((v - ref) * scale);
+    if constexpr (ST == ST_F16DEV) t = enc16(v, ref, scale);
     else t = T(v);
     if constexpr (NT) __builtin_nontemporal_store(t, p);
     else *p = t;
@@ -226,7 +234,7 @@ __device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, i
         asm volatile("" : "+s"(bq));
         GT *p = (GT *)(bq + (uint64_t)o);
         T t;
-        if constexpr (ST == ST_F16DEV) t = T((f[q] - ref[q]) * scale);
+        if constexpr (ST == ST_F16DEV) t = enc16(f[q], ref[q], scale);
         else t = T(f[q]);
         if constexpr (NT) __builtin_nontemporal_store(t, p);
         else *p = t;
@@ -803,9 +811,9 @@ __device__ __forceinline__ bool step3_group8(const typename Form<ST>::T *__restr
         const int fl = node3<C>(f0, fp, fm, role, omega);
         bad = bad || (j <= jl && fl);
         if constexpr (ST == ST_F16DEV) {
-            v0[j] = T((f0 - r0) * a.fp16_scale);
-            o1[j] = T((fp - r1) * a.fp16_scale);
-            v2[j] = T((fm - r1) * a.fp16_scale);
+            v0[j] = enc16(f0, r0, a.fp16_scale);
+            o1[j] = enc16(fp, r1, a.fp16_scale);
+            v2[j] = enc16(fm, r1, a.fp16_scale);
         } else {
             v0[j] = T(f0);
             o1[j] = T(fp);

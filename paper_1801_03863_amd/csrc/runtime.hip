@@ -44,6 +44,15 @@ int hip_fail(hipError_t e, const char *where)
     } while (0)
 
 constexpr int64_t kAlignElems = 64;  // plane alignment (elements)
+// Single-lattice planes of at least 1 MiB carry a pad of 0..8 KiB after their
+// nodes, chosen by the autotuner: the nine plane streams of a tile row start
+// at offsets that differ by the plane stride, and a stride that is a large
+// power of two puts them all on the same memory-channel offset.  Buffers
+// are sized for the largest pad, so the pad can change in place.
+constexpr int64_t kPadMinPlaneBytes = 1 << 20;
+constexpr int32_t kPadMaxBytes = 8192;
+constexpr int32_t kPadDefaultBytes = 2048;
+constexpr int32_t kPadCandidates[] = {0, 1024, 2048, 4096, 8192};
 constexpr int64_t kMaxBatchNodes = int64_t(1) << 22;
 
 size_t elem_bytes(int precision)
@@ -135,6 +144,8 @@ struct lbm_ctx {
     bool base_synced = false;
     int variant = 0;
     int graph_chunk = 0;
+    int32_t pad = -1;        // plane pad in bytes; -1: the context takes none
+    int64_t plane_base = 0;  // plane length before the pad (elements)
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     float scale = 1.0f, iscale = 1.0f;
     std::string arch;
@@ -145,7 +156,15 @@ struct lbm_ctx {
 
 namespace {
 
-int layout(const lbm_params_t *p, int32_t n, int b, std::vector<Inst> *inst, int64_t *elems, int64_t *nodes)
+// Whether a single lattice of these parameters takes a plane pad.
+bool paddable(const lbm_params_t &q, int batch)
+{
+    const int64_t nodes = (int64_t)q.nx * (q.lattice == LBM_D1Q3 ? 1 : q.ny);
+    return !batch && round_up(nodes, kAlignElems) * (int64_t)elem_bytes(q.precision) >= kPadMinPlaneBytes;
+}
+
+int layout(const lbm_params_t *p, int32_t n, int batch, int b, std::vector<Inst> *inst, int64_t *elems,
+           int64_t *nodes)
 {
     int64_t off = 0, nn = 0;
     for (int i = 0; i < n; ++i) {
@@ -155,13 +174,19 @@ int layout(const lbm_params_t *p, int32_t n, int b, std::vector<Inst> *inst, int
         in.ny = q.lattice == LBM_D1Q3 ? 1 : q.ny;
         in.offset = off;
         in.plane = round_up((int64_t)in.nx * in.ny, kAlignElems);
+        int64_t room = in.plane;  // elements reserved per plane
+        if (paddable(q, batch)) {
+            const int64_t eb = (int64_t)elem_bytes(q.precision);
+            room = in.plane + kPadMaxBytes / eb;
+            in.plane += kPadDefaultBytes / eb;
+        }
         in.omega = 1.0 / q.tau;
         const double tau2 = (q.tau2 > 0.0) ? q.tau2 : (8.0 * q.tau - 1.0) / (2.0 * q.tau - 1.0);
         in.omega2 = 1.0 / tau2;
         in.u_lid = q.u_lid;
         in.rho0 = q.rho0;
         feq9(q.rho0, q.u_lid, 0.0, in.lid);
-        off += b * in.plane;
+        off += b * room;
         nn += (int64_t)in.nx * in.ny;
         if (inst) inst->push_back(in);
     }
@@ -218,6 +243,32 @@ void drop_graphs(lbm_ctx *c)
             (void)hipGraphExecDestroy(c->gexec[k]);
             c->gexec[k] = nullptr;
         }
+}
+
+// Move the state to a plane pad of `pad` bytes: each plane's nodes are
+// copied from the current buffer into the other one at the new stride, which
+// then becomes current (both buffers have room for the largest pad).
+int set_pad(lbm_ctx *c, int32_t pad)
+{
+    if (pad == c->pad) return LBM_OK;
+    if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    else HIPCHK(hipDeviceSynchronize());
+    drop_graphs(c);
+    const int64_t eb = (int64_t)c->elem;
+    const int64_t old_plane = c->inst[0].plane;
+    const int64_t new_plane = c->plane_base + pad / eb;
+    const size_t width = (size_t)c->inst[0].nx * (size_t)c->inst[0].ny * (size_t)eb;
+    const char *src = c->buf[c->cur];
+    char *dst = c->buf[c->cur ^ 1];
+    for (int q = 0; q < c->b; ++q)
+        HIPCHK(hipMemcpyAsync(dst + q * new_plane * eb, src + q * old_plane * eb, width, hipMemcpyDeviceToDevice,
+                              c->stream));
+    if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    else HIPCHK(hipDeviceSynchronize());
+    c->cur ^= 1;
+    c->inst[0].plane = new_plane;
+    c->pad = pad;
+    return LBM_OK;
 }
 
 lbm::StepArgs step_args(const lbm_ctx *c, DevStatus *status, int64_t step, const int64_t *base)
@@ -378,7 +429,11 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     const int k = p[0].fp16_exp ? p[0].fp16_exp : 14;
     c->scale = std::ldexp(1.0f, k);
     c->iscale = std::ldexp(1.0f, -k);
-    layout(p, n, c->b, &c->inst, &c->elems, &c->nodes);
+    layout(p, n, batch, c->b, &c->inst, &c->elems, &c->nodes);
+    if (paddable(p[0], batch)) {
+        c->pad = kPadDefaultBytes;
+        c->plane_base = round_up((int64_t)c->inst[0].nx * c->inst[0].ny, kAlignElems);
+    }
     int64_t acc = 0;
     for (int i = 0; i < n; ++i) {
         c->node_prefix.push_back(acc);
@@ -458,11 +513,11 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
 
 extern "C" {
 
-static int ws_bytes(const lbm_params_t *p, int32_t n, size_t *bytes)
+static int ws_bytes(const lbm_params_t *p, int32_t n, int batch, size_t *bytes)
 {
     if (!bytes) return fail(LBM_EINVAL, "null output pointer");
     int64_t elems, nodes;
-    layout(p, n, p[0].lattice == LBM_D1Q3 ? 3 : 9, nullptr, &elems, &nodes);
+    layout(p, n, batch, p[0].lattice == LBM_D1Q3 ? 3 : 9, nullptr, &elems, &nodes);
     *bytes = 2 * buffer_bytes(elems, elem_bytes(p[0].precision));
     return LBM_OK;
 }
@@ -471,14 +526,14 @@ int lbm_workspace_bytes(const lbm_params_t *p, size_t *bytes)
 {
     int rc = check_params(p);
     if (rc) return rc;
-    return ws_bytes(p, 1, bytes);
+    return ws_bytes(p, 1, 0, bytes);
 }
 
 int lbm_workspace_bytes_batch(const lbm_params_t *p, int32_t n, size_t *bytes)
 {
     int rc = check_batch(p, n);
     if (rc) return rc;
-    return ws_bytes(p, n, bytes);
+    return ws_bytes(p, n, 1, bytes);
 }
 
 int lbm_init(const lbm_params_t *p, const double *rho, const double *ux, const double *uy, void *ws,
@@ -564,6 +619,23 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
 
 int lbm_variant_count(const lbm_ctx_t *c) { return c ? variant_count(c) : 0; }
 
+int lbm_set_plane_pad(lbm_ctx_t *c, int32_t pad_bytes)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (c->pad < 0) return fail(LBM_EINVAL, "this context takes no plane pad (batched, or planes under 1 MiB)");
+    if (pad_bytes < 0 || pad_bytes > kPadMaxBytes || pad_bytes % 256 != 0)
+        return fail(LBM_EINVAL, "plane pad must be a multiple of 256 bytes in [0, 8192]");
+    return set_pad(c, pad_bytes);
+}
+
+int lbm_get_layout(const lbm_ctx_t *c, int64_t *plane_stride, int32_t *pad_bytes)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (plane_stride) *plane_stride = c->inst[0].plane;
+    if (pad_bytes) *pad_bytes = c->pad;
+    return LBM_OK;
+}
+
 const char *lbm_variant_name(const lbm_ctx_t *c, int32_t v)
 {
     if (!c) return "?";
@@ -582,14 +654,21 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
     if (cache_path) {
         if (FILE *fh = std::fopen(cache_path, "r")) {
             char line[512];
-            int found = -1;
+            int found = -1, found_pad = -1;
             while (std::fgets(line, sizeof(line), fh)) {
                 char k2[256];
-                int v = -1;
-                if (std::sscanf(line, "%255s %d", k2, &v) == 2 && std::strcmp(k2, key) == 0) found = v;
+                int v = -1, pd = -1;
+                if (std::sscanf(line, "%255s %d %d", k2, &v, &pd) >= 2 && std::strcmp(k2, key) == 0) {
+                    found = v;
+                    found_pad = pd;
+                }
             }
             std::fclose(fh);
             if (found >= 0 && found < variant_count(c)) {
+                if (c->pad >= 0 && found_pad >= 0) {
+                    int rc = lbm_set_plane_pad(c, found_pad);
+                    if (rc) return rc;
+                }
                 if (chosen) *chosen = found;
                 return lbm_set_variant(c, found);
             }
@@ -661,13 +740,35 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
             best_v = t1[k].second;
         }
     }
+    // Stage 3, single lattices with large planes: the plane pad, timed with
+    // the chosen shape in turn over the candidates (the state moves with it).
+    if (c->pad >= 0) {
+        constexpr int np = (int)(sizeof(kPadCandidates) / sizeof(kPadCandidates[0]));
+        float tp[np];
+        for (int k = 0; k < np; ++k) tp[k] = 1e30f;
+        for (int round = 0; round < 3; ++round) {
+            for (int k = 0; k < np; ++k) {
+                int rc = set_pad(c, kPadCandidates[k]);
+                float ms = 0.0f;
+                if (rc == LBM_OK) rc = time_shape(best_v, 4 * reps, 1, ms);
+                if (rc) return rc;
+                tp[k] = std::min(tp[k], ms);
+            }
+        }
+        int kb = 0;
+        for (int k = 1; k < np; ++k)
+            if (tp[k] < tp[kb]) kb = k;
+        int rc = set_pad(c, kPadCandidates[kb]);
+        if (rc) return rc;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     int rc = lbm_set_variant(c, best_v);
     if (rc) return rc;
     if (cache_path) {
         if (FILE *fh = std::fopen(cache_path, "a")) {
-            std::fprintf(fh, "%s %d\n", key, best_v);
+            if (c->pad >= 0) std::fprintf(fh, "%s %d %d\n", key, best_v, c->pad);
+            else std::fprintf(fh, "%s %d\n", key, best_v);
             std::fclose(fh);
         }
     }

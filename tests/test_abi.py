@@ -79,10 +79,21 @@ def test_error_strings(B):
 
 
 def test_single_lattice_workspace_has_no_batch_size_limit(B):
+    # Planes of at least 1 MiB reserve room for the largest plane pad (8 KiB).
     p = B.make_params("d2q9", "minxent4", "cavity", "fp32_newton64", 8192, 8192, 0.6)
-    assert B.lbm_workspace_bytes(p) == 2 * 9 * 8192 * 8192 * 4
+    assert B.lbm_workspace_bytes(p) == 2 * 9 * (8192 * 8192 * 4 + 8192)
     with pytest.raises(B.LbmError):
         B.lbm_workspace_bytes_batch([p])
+
+
+def test_plane_pad_room_only_for_large_single_planes(B):
+    # 512 x 512 FP32 is exactly 1 MiB per plane: padded; one row less is not.
+    big = B.make_params("d2q9", "minxent4", "cavity", "fp32", 512, 512, 0.6)
+    assert B.lbm_workspace_bytes(big) == 2 * 9 * (512 * 512 * 4 + 8192)
+    small = B.make_params("d2q9", "minxent4", "cavity", "fp32", 512, 511, 0.6)
+    assert B.lbm_workspace_bytes(small) == 2 * ((9 * 512 * 511 * 4 + 255) // 256 * 256)
+    # Batches never take a pad.
+    assert B.lbm_workspace_bytes_batch([big]) == 2 * 9 * 512 * 512 * 4
 
 
 def test_lattice_size_limit(B):
@@ -93,7 +104,7 @@ def test_lattice_size_limit(B):
         B.lbm_workspace_bytes(big)
     assert ei.value.code == B.LBM_EINVAL
     ok = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 32767, 32768, 0.6)
-    plane = (32767 * 32768 + 63) // 64 * 64
+    plane = (32767 * 32768 + 63) // 64 * 64 + 8192 // 2
     assert B.lbm_workspace_bytes(ok) == 2 * ((9 * plane * 2 + 255) // 256 * 256)
 
 

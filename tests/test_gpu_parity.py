@@ -341,3 +341,109 @@ def test_copy_kernel():
     b.lbm_copy_kernel(dst, src, src.numel() * 4)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+# --------------------------------------------------------------------------
+# Plane pad (single lattices with planes of at least 1 MiB)
+# --------------------------------------------------------------------------
+
+def test_plane_pad_moves_the_state_bitwise():
+    # 1024 x 300 FP32: 1.2 MB planes, so the context takes a pad.  Pads
+    # changed mid-run (with graph replay around them) leave the trajectory
+    # bitwise equal to a run that keeps the default pad.
+    nx, ny = 1024, 300
+    rho, ux, uy = smooth_fields(nx, ny, seed=31)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp32", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    ref = b.lbm_init(p, rho, ux, uy)
+    c = b.lbm_init(p, rho, ux, uy)
+    try:
+        base = (nx * ny + 63) // 64 * 64
+        assert b.lbm_get_layout(c) == (base + 2048 // 4, 2048)
+        b.lbm_step(ref, 25)
+        b.lbm_set_graph_chunk(c, 4)
+        b.lbm_step(c, 7)
+        for pad in (0, 8192, 256, 4096):
+            b.lbm_set_plane_pad(c, pad)
+            assert b.lbm_get_layout(c) == (base + pad // 4, pad)
+            b.lbm_step(c, 6 if pad != 4096 else 0)
+        assert b.lbm_info(c)["steps_done"] == 25
+        assert np.array_equal(b.lbm_get_populations(ref, 9), b.lbm_get_populations(c, 9))
+        r1, r2 = b.lbm_status(ref), b.lbm_status(c)
+        assert r1 == r2 and not r1["unstable"]
+    finally:
+        b.lbm_free(ref)
+        b.lbm_free(c)
+
+
+def test_plane_pad_fp64_against_oracle():
+    # The FP64 path with a non-default pad still matches the oracle.
+    nx, ny = 520, 260  # 1.08 MB planes
+    rho, ux, uy = smooth_fields(nx, ny, seed=32)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    ctx = b.lbm_init(p, rho, ux, uy)
+    try:
+        b.lbm_set_plane_pad(ctx, 1024)
+        b.lbm_step(ctx, 12)
+        r, u, v = b.lbm_moments(ctx)
+    finally:
+        b.lbm_free(ctx)
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=12, u_lid=0.1)
+    g = {"rho": r.reshape(ny, nx), "ux": u.reshape(ny, nx), "uy": v.reshape(ny, nx)}
+    assert_close(g, o, fluid_mask("d2q9", "cavity", nx, ny), TOL64, label="pad 1024")
+
+
+def test_plane_pad_argument_errors():
+    b = B()
+    big = b.make_params("d2q9", "minxent4", "cavity", "fp32", 1024, 300, 0.6, 0.0, 0.1, 1.0)
+    small = b.make_params("d2q9", "minxent4", "cavity", "fp32", 45, 37, 0.6, 0.0, 0.1, 1.0)
+    r, u, v = smooth_fields(1024, 300, seed=33)
+    c = b.lbm_init(big, r, u, v)
+    rs, us, vs = smooth_fields(45, 37, seed=34)
+    s = b.lbm_init(small, rs, us, vs)
+    bt = b.lbm_init_batch([big], r, u, v)
+    try:
+        for bad in (-256, 100, 8448):
+            with pytest.raises(b.LbmError) as ei:
+                b.lbm_set_plane_pad(c, bad)
+            assert ei.value.code == b.LBM_EINVAL
+        for ctx in (s, bt):
+            with pytest.raises(b.LbmError):
+                b.lbm_set_plane_pad(ctx, 0)
+            assert b.lbm_get_layout(ctx)[1] == -1
+        assert b.lbm_get_layout(c)[1] == 2048  # errors left the pad alone
+        b.lbm_step(c, 3)
+        assert not b.lbm_status(c)["unstable"]
+    finally:
+        b.lbm_free(c)
+        b.lbm_free(s)
+        b.lbm_free(bt)
+
+
+def test_autotune_tunes_the_plane_pad_and_keeps_the_state(tmp_path):
+    nx, ny = 1024, 300
+    rho, ux, uy = smooth_fields(nx, ny, seed=35)
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.6, 0.0, 0.1, 1.0)
+    c1 = b.lbm_init(p, rho, ux, uy)
+    c2 = b.lbm_init(p, rho, ux, uy)
+    c3 = b.lbm_init(p, rho, ux, uy)
+    cache = str(tmp_path / "tune.txt")
+    try:
+        for c in (c1, c2, c3):
+            b.lbm_step(c, 5)
+        v = b.lbm_autotune(c2, cache)
+        pad = b.lbm_get_layout(c2)[1]
+        assert pad in (0, 1024, 2048, 4096, 8192)
+        fields = open(cache).read().split()
+        assert len(fields) == 3 and int(fields[1]) == v and int(fields[2]) == pad
+        assert b.lbm_autotune(c3, cache) == v and b.lbm_get_layout(c3)[1] == pad  # from the cache
+        for c in (c1, c2, c3):
+            b.lbm_step(c, 5)
+        f1 = b.lbm_get_populations(c1, 9)
+        assert np.array_equal(f1, b.lbm_get_populations(c2, 9))
+        assert np.array_equal(f1, b.lbm_get_populations(c3, 9))
+    finally:
+        for c in (c1, c2, c3):
+            b.lbm_free(c)
