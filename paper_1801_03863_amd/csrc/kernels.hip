@@ -241,6 +241,68 @@ __device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, i
     }
 }
 
+// Address of a block-uniform pointer, read from the first lane so that it
+// lives in scalar registers (each half through uint32_t: readfirstlane
+// returns a signed int, and widening must zero-extend it).
+__device__ __forceinline__ uint64_t uniform_addr(const void *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+// Batched D2Q9: pull the nine raw populations of a node of one instance,
+// whose planes start at the block-uniform address s (stride P elements),
+// from byte offsets of rows (rc own, rm below, rp above) and columns (cc
+// own, cm left, cp right).  An instance holds fewer than 2^22 nodes, so
+// every offset fits 32 bits and each load takes the scalar-base + 32-bit
+// vector-offset form.  NL as for pull9_cols.
+template <int ST, int NL>
+__device__ __forceinline__ void pull9_inst(uint64_t s, int64_t P, uint32_t rc, uint32_t rm, uint32_t rp,
+                                           uint32_t cc, uint32_t cm, uint32_t cp, typename Form<ST>::T (&r)[9])
+{
+    using T = typename Form<ST>::T;
+    using GT = const __attribute__((address_space(1))) T;
+    constexpr bool A = NL == 1, U = NL != 0;
+    constexpr bool nt[9] = {U, A, U, A, U, A, A, A, A};
+    const uint32_t o[9] = {rc + cc, rc + cm, rm + cc, rc + cp, rp + cc, rm + cm, rm + cp, rp + cp, rp + cm};
+    const uint64_t PB = (uint64_t)P * sizeof(T);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        uint64_t bq = s + q * PB;
+        asm volatile("" : "+s"(bq));
+        uint32_t oq = o[q];
+        asm volatile("" : "+v"(oq));
+        GT *p = (GT *)(bq + (uint64_t)oq);
+        if (nt[q]) r[q] = __builtin_nontemporal_load(p);
+        else r[q] = *p;
+    }
+}
+
+// Batched D2Q9: write the nine populations of the node at byte offset o of
+// the instance whose planes start at the block-uniform address d.
+template <int ST, bool NT = false>
+__device__ __forceinline__ void push9_inst(uint64_t d, int64_t P, uint32_t o, const typename Form<ST>::C (&f)[9],
+                                           const typename Form<ST>::C (&ref)[9], float scale)
+{
+    using T = typename Form<ST>::T;
+    using GT = __attribute__((address_space(1))) T;
+    const uint64_t PB = (uint64_t)P * sizeof(T);
+    asm volatile("" : "+v"(o));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        uint64_t bq = d + q * PB;
+        asm volatile("" : "+s"(bq));
+        GT *p = (GT *)(bq + (uint64_t)o);
+        T t;
+        if constexpr (ST == ST_F16DEV) t = enc16(f[q], ref[q], scale);
+        else t = T(f[q]);
+        if constexpr (NT) __builtin_nontemporal_store(t, p);
+        else *p = t;
+    }
+}
+
 // Write the nine post-collision populations of node index i.
 template <int ST, bool NT = false>
 __device__ __forceinline__ void push9(typename Form<ST>::T *__restrict__ d, int64_t P, int i,
@@ -594,12 +656,24 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     const Nb n = neighbours(x, y, nx, ny, a.bc);
-    const typename Form<ST>::T *s = src + in.offset;
+    constexpr uint32_t E = sizeof(typename Form<ST>::T);
+    // Row byte offsets without multiplies: y*nx is node - x, and the rows
+    // below and above are one row away unless the wrap/clamp rule applies.
+    const uint32_t rc = (uint32_t)(node - x) * E, rb = (uint32_t)nx * E;
+    const uint32_t rm = n.ym == y - 1 ? rc - rb : (uint32_t)n.ym * rb;
+    const uint32_t rp = n.yp == y + 1 ? rc + rb : (uint32_t)n.yp * rb;
     C f[9];
-    pull9<ST, nl_mode(NT)>(s, P, x, y, nx, n, ref, a.fp16_iscale, f);
+    {
+        typename Form<ST>::T raw[9];
+        pull9_inst<ST, nl_mode(NT)>(uniform_addr(src + in.offset), P, rc, rm, rp, (uint32_t)x * E,
+                                    (uint32_t)n.xm * E, (uint32_t)n.xp * E, raw);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
+    }
     const int role = role9(x, y, nx, ny, a.bc);
     const int fl = node9<ST, CO>(f, role, in);
-    if (valid) push9<ST, (NT & 2) != 0>(dst + in.offset, P, node, f, ref, a.fp16_scale);
+    if (valid)
+        push9_inst<ST, (NT & 2) != 0>(uniform_addr(dst + in.offset), P, (uint32_t)node * E, f, ref, a.fp16_scale);
     const int guarded = __popcll(__ballot(valid && (fl & 2)));
     report(a.status + i, valid && (fl & 1), guarded, a.step, a.step_base);
 }
@@ -1167,9 +1241,17 @@ hipError_t dispatch9c(int coll, int v, const void *src, void *dst, const StepArg
 
 
 template <int ST, int CO>
-hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, hipStream_t s)
 {
     using T = typename Form<ST>::T;
+    // Tiles run in launch order; shapes 5 and 6 are 3 and 4 with tiles in
+    // XCD-banded order instead (measured slower, kept as candidates).
+    StepArgs a = a_in;
+    a.xcd_swizzle = 0;
+    if (v >= 5) {
+        a.xcd_swizzle = 1;
+        v -= 2;
+    }
     switch (v) {
     case 0: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 0>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 1: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 128, 0>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;
@@ -1254,18 +1336,30 @@ struct ShapeB {
 constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"},
                                 {256, 1, "batch 256 nodes/block nt-load nt-store"},
                                 {256, 1, "batch 256 nodes/block nt-store"},
-                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store"}};
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store"},
+                                {256, 1, "batch 256 nodes/block nt-store, XCD-banded"},
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store, XCD-banded"}};
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block nt-load nt-store"},
                                 {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors"},
                                 {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
-                                {128, 8, "batch 128 groups of 8 nodes, 16-byte vectors nt-load nt-store"}};
+                                {128, 8, "batch 128 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
+                                {128, 1, "batch 128x1 nodes/block, XCD-banded"},
+                                {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors, XCD-banded"}};
 
 template <int ST>
-hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a_in, hipStream_t s)
 {
     using T = typename Form<ST>::T;
+    // Tiles run in launch order; shapes 8 and 9 are 1 and 5 with tiles in
+    // XCD-banded order instead (measured slower, kept as candidates).
+    StepArgs a = a_in;
+    a.xcd_swizzle = 0;
+    if (v >= 8) {
+        a.xcd_swizzle = 1;
+        v = v == 8 ? 1 : 5;
+    }
     switch (v) {
     case 0: hipLaunchKernelGGL((k_d1q3_batch<ST, 256, 1>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 1: hipLaunchKernelGGL((k_d1q3_batch<ST, 128, 1>), dim3(a.ntiles), dim3(128), 0, s, (const T *)src, (T *)dst, a); break;

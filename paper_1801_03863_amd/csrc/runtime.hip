@@ -283,7 +283,7 @@ lbm::StepArgs step_args(const lbm_ctx *c, DevStatus *status, int64_t step, const
     a.step = step;
     a.bc = c->p.bc;
     a.ntiles = c->ntiles;
-    a.xcd_swizzle = 1;
+    a.xcd_swizzle = 0;  // launch order; each launcher sets its own
     a.fp16_scale = c->scale;
     a.fp16_iscale = c->iscale;
     return a;
