@@ -186,6 +186,39 @@ def moving_flow(B, torch, I, n, tau, steps, warmup, tune_cache):
     return out
 
 
+def launch_bound(B, torch, I, tune_cache):
+    """The two small configurations, whose steps are a few microseconds of
+    work: the 800-node D1Q3 shock tube (400 steps, FP64) and the 256^2 cavity
+    (20000 steps, FP64), each timed with one launch per step and replayed
+    from captured HIP graphs of 100 steps (the whole run is one timed
+    region; results are bitwise the same)."""
+    out = {}
+    for name, c in (("tube800_fp64", I.shock_tube_800()), ("cavity256_fp64", I.cavity_256())):
+        lat = c.get("lattice", "d2q9")
+        coll = "srt" if lat == "d1q3" else "minxent4"
+        p = B.make_params(lat, coll, c.get("bc", "cavity"), "fp64", c["nx"], c["ny"], c["tau"], 0.0, c["u_lid"], 1.0)
+        res = {}
+        for chunk in (0, 100):
+            ctx = B.lbm_init(p, c["rho"], c["ux"], c["uy"])
+            B.lbm_autotune(ctx, tune_cache)
+            if chunk:
+                B.lbm_set_graph_chunk(ctx, chunk)
+            B.lbm_step(ctx, min(c["steps"], 200))  # warm-up (and graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.lbm_step(ctx, c["steps"])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            nodes = B.lbm_info(ctx)["nodes"]
+            B.lbm_free(ctx)
+            res["graph%d" % chunk if chunk else "plain"] = {
+                "mlups": round(nodes * c["steps"] / wall / 1e6, 1), "us_per_step": round(wall / c["steps"] * 1e6, 2)}
+        res["nodes"] = nodes
+        res["steps"] = c["steps"]
+        out[name] = res
+    return out
+
+
 def fp16_cavity(B, torch, I, steps, warmup, tune_cache):
     """8192^2 cavity, lid 0.05, Re 5000: FP16 deviation storage against FP64."""
     import numpy as np
@@ -352,6 +385,7 @@ def main():
                                                  args.tune_cache)
         out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup, args.tune_cache,
                                                args.batch_graph_chunk)
+        out["launch_bound"] = launch_bound(B, torch, I, args.tune_cache)
     out["copy_kernel_gbs"] = round(copy_bandwidth(B, torch), 1)
     out["kernel_source_sha256_16"] = digest
     if not args.no_cpu_baseline:
