@@ -10,6 +10,7 @@
 """
 import json
 import os
+import shutil
 
 import numpy as np
 import pytest
@@ -19,6 +20,17 @@ from tests.gpu_helpers import B, fluid_mask, gpu_run, orc_run
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CACHE = os.path.join(ROOT, "paper_1801_03863_amd", "tune_cache_gfx950.txt")
+
+
+def bench_tuning(b, ctx, tmp_path):
+    """The launch configuration bench.py times: launch shape and plane pad
+    from the committed tuning cache, read through a copy so that a missing
+    key is tuned without touching the package's file."""
+    path = tmp_path / "tune_cache.txt"
+    if os.path.exists(CACHE):
+        shutil.copy(CACHE, path)
+    return b.lbm_autotune(ctx, str(path))
 
 
 def sample_points(n, count, seed):
@@ -45,7 +57,7 @@ def windowed_oracle(c, n, steps, x, y):
 @pytest.mark.parametrize("n,precision,tol_rho,tol_u", [
     (4096, "fp64", 1e-12, 1e-12), (4096, "fp32_newton64", 1e-7, 5e-6), (4096, "fp32", 1e-6, 1e-5),
     (8192, "fp16dev", 5e-5, 2e-3)])
-def test_benchmark_cavity_sampled(n, precision, tol_rho, tol_u):
+def test_benchmark_cavity_sampled(n, precision, tol_rho, tol_u, tmp_path):
     c = I.cavity_4096_params() if n == 4096 else I.cavity_8192_params()
     n, steps = c["nx"], 6
     r, u, v = I.cavity_fields(n, 1.0, c["seed"])
@@ -53,7 +65,7 @@ def test_benchmark_cavity_sampled(n, precision, tol_rho, tol_u):
     p = b.make_params("d2q9", "minxent4", "cavity", precision, n, n, c["tau"], 0.0, c["u_lid"], 1.0)
     ctx = b.lbm_init(p, r, u, v)
     try:
-        b.lbm_autotune(ctx)
+        bench_tuning(b, ctx, tmp_path)
         b.lbm_step(ctx, steps)
         gr, gu, gv = (a.reshape(n, n) for a in b.lbm_moments(ctx))
         st = b.lbm_status(ctx)
@@ -315,7 +327,7 @@ def test_lds_resident_persistent_batch_is_bitwise(precision, steps):
         assert a_["guarded"] == b_["guarded"]
 
 
-def test_full_cavity_batch_5000_steps_against_oracle():
+def test_full_cavity_batch_5000_steps_against_oracle(tmp_path):
     # The whole 512-cavity batch (22.3 M nodes, sides 32..512, Re 100..10000,
     # lid 0.1) for its full 5000 steps in FP64; the oracle reruns the four
     # smallest instances whole.  Instances that blow up are compared by status
@@ -330,7 +342,8 @@ def test_full_cavity_batch_5000_steps_against_oracle():
     steps = 5000
     ctx = b.lbm_init_batch(params, np.concatenate(rs), np.concatenate(us), np.concatenate(vs))
     try:
-        b.lbm_autotune(ctx)
+        bench_tuning(b, ctx, tmp_path)
+        b.lbm_set_graph_chunk(ctx, 50)  # as bench.py times batches
         b.lbm_step(ctx, steps)
         R, U, V = b.lbm_moments(ctx)
         sts = b.lbm_status_batch(ctx, len(insts))
@@ -356,7 +369,7 @@ def test_full_cavity_batch_5000_steps_against_oracle():
             assert err <= 1e-12, (i, n, f, err)
 
 
-def test_full_tube_batch_1000_steps_against_oracle():
+def test_full_tube_batch_1000_steps_against_oracle(tmp_path):
     # The whole 4096-tube batch (62.6 M nodes) for its full 1000 steps in
     # FP64; the oracle reruns the six shortest tubes whole.
     tubes = I.tube_batch(count=4096)
@@ -369,7 +382,8 @@ def test_full_tube_batch_1000_steps_against_oracle():
     steps = 1000
     ctx = b.lbm_init_batch(params, np.concatenate(rs), np.concatenate(us), None)
     try:
-        b.lbm_autotune(ctx)
+        bench_tuning(b, ctx, tmp_path)
+        b.lbm_set_graph_chunk(ctx, 50)  # as bench.py times batches
         b.lbm_step(ctx, steps)
         R, U, _ = b.lbm_moments(ctx)
         sts = b.lbm_status_batch(ctx, len(tubes))
@@ -391,7 +405,7 @@ def test_full_tube_batch_1000_steps_against_oracle():
         assert er <= 1e-12 and eu <= 1e-12, (i, n, er, eu)
 
 
-def test_benchmark_cavity_fp64_60_steps_sampled():
+def test_benchmark_cavity_fp64_60_steps_sampled(tmp_path):
     # The 4096^2 benchmark cavity in FP64 for 60 steps in the autotuned shape;
     # 12 sampled nodes (corners, lid row, walls, interior) against windowed
     # oracle runs of (2*61+1)^2 nodes each.
@@ -402,7 +416,7 @@ def test_benchmark_cavity_fp64_60_steps_sampled():
     p = b.make_params("d2q9", "minxent4", "cavity", "fp64", n, n, c["tau"], 0.0, c["u_lid"], 1.0)
     ctx = b.lbm_init(p, r, u, v)
     try:
-        b.lbm_autotune(ctx)
+        bench_tuning(b, ctx, tmp_path)
         b.lbm_step(ctx, steps)
         gr, gu, gv = (a.reshape(n, n) for a in b.lbm_moments(ctx))
         assert not b.lbm_status(ctx)["unstable"]
