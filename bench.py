@@ -316,6 +316,7 @@ def main():
                     help="autotuner cache (entries are keyed by a hash of the kernel sources)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and FP16 workloads")
     ap.add_argument("--extra-steps", type=int, default=500)
+    ap.add_argument("--no-launch-bound", action="store_true", help="skip the two small launch-bound configurations")
     ap.add_argument("--batch-graph-chunk", type=int, default=50,
                     help="steps per captured HIP graph for the batched workloads (0: plain launches)")
     args = ap.parse_args()
@@ -385,7 +386,8 @@ def main():
                                                  args.tune_cache)
         out["fp16dev_tubes_4096"] = fp16_tubes(B, torch, I, args.extra_steps, args.warmup, args.tune_cache,
                                                args.batch_graph_chunk)
-        out["launch_bound"] = launch_bound(B, torch, I, args.tune_cache)
+        if not args.no_launch_bound:
+            out["launch_bound"] = launch_bound(B, torch, I, args.tune_cache)
     out["copy_kernel_gbs"] = round(copy_bandwidth(B, torch), 1)
     out["kernel_source_sha256_16"] = digest
     if not args.no_cpu_baseline:

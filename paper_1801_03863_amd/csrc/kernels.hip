@@ -10,7 +10,10 @@
 //
 // Layout: structure of arrays, one plane of nx*ny values per direction,
 // x fastest, so every plane read is a unit-stride row shifted by at most one
-// element and every write is aligned and unit-stride.  Populations are read
+// element and every write is aligned and unit-stride.  Planes follow each
+// other at a stride of the node count rounded up to 64 elements, plus, for a
+// large single lattice, a tuned pad that is a multiple of 256 bytes, so every
+// plane starts 256-byte aligned.  Populations are read
 // and written exactly once per step.  The kernels are bound by HBM bandwidth
 // in FP64, FP32 and FP32-storage/FP64-compute forms, and by VALU issue (the
 // logarithms, reciprocals and 4 x 4 solve of the Newton step) when the
@@ -841,8 +844,8 @@ __device__ __forceinline__ void st8(T *p, const T (&v)[8])
 }
 
 // Eight consecutive nodes x0 .. x0+7 of one D1Q3 lattice (x0 a multiple of 8,
-// x0 < nx; plane bases 64-element aligned, planes padded to 64 elements, so
-// each group is 16-byte aligned and inside its plane).  Every plane moves as
+// x0 < nx; plane bases 256-byte aligned and plane lengths rounded up to 64
+// elements, so each group is 16-byte aligned and inside its plane).  Every plane moves as
 // 16-byte vectors; the two values shifted in from outside the group (plane 1
 // from the left, plane 2 from the right) take one scalar load each, with the
 // same wrap/clamp rule as the one-node form, so results are bitwise equal to
