@@ -1,0 +1,65 @@
+"""Seeded random sweep of small configurations: FP64 GPU path against the
+oracle at 1e-12 (fields on fluid nodes, and the status words), over lattice,
+size (ragged, one tile to several), boundary kind, collision rule, tau, lid
+speed, step count and launch shape.  Each case prints its parameters first,
+so a failure names the case."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import B, field_errors, fluid_mask, gpu_run, orc_run, smooth_fields
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+CASES = 48
+
+
+def case(k):
+    rng = np.random.default_rng(4200 + k)
+    lattice = "d1q3" if k % 6 == 5 else "d2q9"
+    if lattice == "d1q3":
+        nx, ny = int(rng.integers(3, 5000)), 1
+        bc = ["periodic", "tube", "cavity"][int(rng.integers(0, 3))]
+        coll = "srt"
+    else:
+        nx, ny = int(rng.integers(3, 700)), int(rng.integers(3, 260))
+        bc = ["cavity", "periodic", "tube", "box"][int(rng.integers(0, 4))]
+        coll = ["minxent4", "minxent2", "srt", "trt", "mrt"][int(rng.integers(0, 5))]
+    tau = float(rng.uniform(0.52, 1.5))
+    u_lid = float(rng.uniform(0.0, 0.1)) if bc == "cavity" else 0.0
+    steps = int(rng.integers(1, 25))
+    return dict(lattice=lattice, nx=nx, ny=ny, bc=bc, coll=coll, tau=tau, u_lid=u_lid, steps=steps,
+                seed=int(rng.integers(0, 2**31)), pick=float(rng.uniform()))
+
+
+@pytest.mark.parametrize("k", range(CASES))
+def test_random_configuration_against_oracle(k):
+    c = case(k)
+    print("case", k, c, flush=True)
+    b = B()
+    if c["lattice"] == "d1q3":
+        rng = np.random.default_rng(c["seed"])
+        rho = 1.0 + 0.2 * rng.uniform(-1, 1, c["nx"])
+        ux = 0.05 * rng.uniform(-1, 1, c["nx"])
+        uy = None
+        fields = ("rho", "ux")
+    else:
+        rho, ux, uy = smooth_fields(c["nx"], c["ny"], seed=c["seed"])
+        fields = ("rho", "ux", "uy")
+    p = b.make_params(c["lattice"], c["coll"], c["bc"], "fp64", c["nx"], c["ny"], c["tau"], 0.0, c["u_lid"], 1.0)
+    ctx = b.lbm_init(p, rho, ux, uy)
+    nv = b.lbm_variant_count(ctx)
+    b.lbm_free(ctx)
+    variant = min(int(c["pick"] * nv), nv - 1)
+    g = gpu_run(c["lattice"], c["coll"], c["bc"], "fp64", c["nx"], c["ny"], c["tau"], rho, ux, uy,
+                steps=c["steps"], u_lid=c["u_lid"], variant=variant)
+    o = orc_run(c["lattice"], c["coll"], c["bc"], c["nx"], c["ny"], c["tau"], rho, ux, uy, steps=c["steps"],
+                u_lid=c["u_lid"])
+    assert g["status"]["unstable"] == o["unstable"], c
+    assert g["status"]["guarded"] == o["guarded"], c
+    if o["unstable"]:
+        assert g["status"]["first_step"] == o["first_step"], c
+        return
+    errs = field_errors(g, o, fluid_mask(c["lattice"], c["bc"], c["nx"], c["ny"]), fields)
+    print("variant", variant, {f: ("%.1e" % e[0], "%.1e" % e[1]) for f, e in errs.items()}, flush=True)
+    for f, (emax, el2) in errs.items():
+        assert emax <= TOL64 and el2 <= TOL64, (k, f, emax, el2)
