@@ -170,15 +170,21 @@ __device__ __forceinline__ void ln1p4_lean(const double (&t)[4], double (&out)[4
     ln1p4(t, out);
 }
 
-// Single precision.  When every |t| < 2^-8 (chosen per wave): the series
-// t - t^2/2 + t^3/3, whose first omitted term is below 2^-24 |t| / 4 (three
-// operations instead of a quarter-rate hardware logarithm and its range
+// Single precision, chosen per lane from the largest |t| of the four:
+// |t| < 2^-12 (fluid close to rest), t - t^2/2, first omitted term below
+// 2^-24 |t| / 3; |t| < 2^-8, t - t^2/2 + t^3/3, below 2^-24 |t| / 4 (two or
+// three operations instead of a quarter-rate hardware logarithm and its range
 // handling).  Otherwise logf(1 + t): t = y - 1 is exact for y in [1/2, 2],
 // so 1 + t gives y back (outside that range one more rounding).
 __device__ __forceinline__ void ln1p4(const float (&t)[4], float (&out)[4])
 {
     const float mt = __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(t[0]), __builtin_fabsf(t[1])),
                                      __builtin_fmaxf(__builtin_fabsf(t[2]), __builtin_fabsf(t[3])));
+    if (mt < 0.000244140625f) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[i] = __builtin_fmaf(t[i] * t[i], -0.5f, t[i]);
+        return;
+    }
     if (mt < 0.00390625f) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)

@@ -641,6 +641,7 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
                                                     typename Form<ST>::T *__restrict__ dst, StepArgs a)
 {
     using C = typename Form<ST>::C;
+    if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(2);  // until the loads are issued
     int t = blockIdx.x;
     if (a.xcd_swizzle) t = xcd_remap(t, gridDim.x);
     const int i = a.tile_inst[t];
@@ -670,6 +671,7 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
         typename Form<ST>::T raw[9];
         pull9_inst<ST, nl_mode(NT)>(uniform_addr(src + in.offset), P, rc, rm, rp, (uint32_t)x * E,
                                     (uint32_t)n.xm * E, (uint32_t)n.xp * E, raw);
+        if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
     }
@@ -1251,7 +1253,7 @@ hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, h
     // XCD-banded order instead (measured slower, kept as candidates).
     StepArgs a = a_in;
     a.xcd_swizzle = 0;
-    if (v >= 5) {
+    if (v == 5 || v == 6) {
         a.xcd_swizzle = 1;
         v -= 2;
     }
@@ -1261,6 +1263,8 @@ hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, h
     case 2: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 3>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 3: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 2>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 4: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 6>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 7: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 10>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
+    case 8: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 14>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1341,7 +1345,9 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {256, 1, "batch 256 nodes/block nt-store"},
                                 {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store"},
                                 {256, 1, "batch 256 nodes/block nt-store, XCD-banded"},
-                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store, XCD-banded"}};
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store, XCD-banded"},
+                                {256, 1, "batch 256 nodes/block nt-store prio"},
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store prio"}};
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block nt-load nt-store"},
