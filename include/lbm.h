@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 /* Error codes. */
 #define LBM_OK 0
@@ -102,6 +102,9 @@ typedef struct lbm_status {
     uint32_t flags;      /* bit 0: UNSTABLE, bit 1: GUARDED (some node skipped its Newton step) */
     int32_t reserved;
     int64_t first_step;  /* step (0-based) of the first UNSTABLE event, -1 if none */
+    int64_t first_node;  /* the smallest node index x + y*nx unstable at first_step, -1 if none;
+                            for lbm_status() over a batch, in the instances' concatenated node
+                            order.  Steps beyond 2^32 - 1 are recorded as 2^32 - 1. */
     int64_t guarded;     /* node-steps that kept their Newton start point: a start population
                             <= 0 or not finite, or (FP64 arithmetic) a product of the nine
                             below the smallest normal double */

@@ -508,6 +508,7 @@ typedef struct {
     int32_t unstable;   /* 1 if some fluid post-collision population was negative or not finite */
     int32_t first_step; /* step of the first such event, -1 if none */
     int64_t guarded;    /* node-steps where the Newton start point left p > 0 */
+    int64_t first_node; /* smallest node index x + y*nx (whole lattice) unstable at first_step, -1 if none */
 } orc_status;
 
 /* Node role from its global coordinates.  Tube: walls at x = 0 and x = nx-1
@@ -605,6 +606,7 @@ int orc_run_window(const orc_params *P, int x0, int y0, int wx, int wy,
     }
     st->unstable = 0;
     st->first_step = -1;
+    st->first_node = -1;
     st->guarded = 0;
     double flid[9];
     orc_feq_d2q9(P->rho0, P->u_lid, 0.0, flid);
@@ -635,7 +637,12 @@ int orc_run_window(const orc_params *P, int x0, int y0, int wx, int wy,
                 fluid_collide(P, loc, out, st);
                 for (int a = 0; a < b; ++a)
                     if (!(out[a] >= 0.0) || !isfinite(out[a])) {
-                        if (!st->unstable) st->first_step = (int32_t)s;
+                        /* nodes are visited in increasing index, so the first one
+                         * found in the first unstable step is the smallest */
+                        if (!st->unstable) {
+                            st->first_step = (int32_t)s;
+                            st->first_node = (int64_t)(y0 + (int)(i / (size_t)wx)) * P->nx + (x0 + (int)(i % (size_t)wx));
+                        }
                         st->unstable = 1;
                     }
             } else if (role[i] == ROLE_WALL) {

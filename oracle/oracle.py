@@ -58,6 +58,7 @@ class Status(ctypes.Structure):
         ("unstable", ctypes.c_int32),
         ("first_step", ctypes.c_int32),
         ("guarded", ctypes.c_int64),
+        ("first_node", ctypes.c_int64),
     ]
 
 
@@ -204,7 +205,8 @@ def run(lattice, collision, bc, nx, ny, tau, rho, ux, uy=None, steps=1, tau2=0.0
         raise ValueError("oracle run rejected its parameters")
     shape = (wx,) if lattice == D1Q3 else (wy, wx)
     out = {"rho": ro.reshape(shape), "ux": uo.reshape(shape), "uy": vo.reshape(shape),
-           "unstable": bool(st.unstable), "first_step": st.first_step, "guarded": st.guarded}
+           "unstable": bool(st.unstable), "first_step": st.first_step, "first_node": st.first_node,
+           "guarded": st.guarded}
     if want_f:
         out["f"] = fo.reshape((b,) + shape)
     return out

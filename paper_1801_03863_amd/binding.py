@@ -64,6 +64,7 @@ class lbm_status_t(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_int32),
         ("first_step", ctypes.c_int64),
+        ("first_node", ctypes.c_int64),
         ("guarded", ctypes.c_int64),
     ]
 
@@ -262,7 +263,7 @@ def lbm_set_populations(ctx, f):
 
 def _status_dict(s):
     return {"flags": s.flags, "unstable": bool(s.flags & STATUS_UNSTABLE), "guarded": s.guarded,
-            "first_step": s.first_step}
+            "first_step": s.first_step, "first_node": s.first_node}
 
 
 def lbm_status(ctx):

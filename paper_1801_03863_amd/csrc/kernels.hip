@@ -389,20 +389,38 @@ __device__ __forceinline__ void push_lid(typename Form<ST>::T *__restrict__ d, i
 }
 
 // Wave-level status update: one atomic per wave and kind.
-__device__ __forceinline__ void report(DevStatus *st, bool unstable, int guarded_in_wave, int64_t step,
+// Key of an unstable event: the step in the high word (saturating at 2^32 -
+// 1), the node index (x + y nx within its instance) in the low word, so that
+// the smallest key is the first step's smallest node.
+__device__ __forceinline__ uint64_t event_key(int64_t step, int node)
+{
+    const uint64_t s = step < 0xffffffffll ? (uint64_t)step : 0xffffffffull;
+    return (s << 32) | (uint32_t)node;
+}
+
+// Sentinel of a lane's unstable-node record: no unstable node.
+constexpr int kNoNode = 0x7fffffff;
+
+// bad_node: the smallest unstable node index of this lane in this launch, or
+// kNoNode.  One atomic per wave and kind; the wave's smallest unstable node
+// is found by a butterfly minimum only in waves that have one.
+__device__ __forceinline__ void report(DevStatus *st, int bad_node, int guarded_in_wave, int64_t step,
                                        const int64_t *step_base)
 {
-    const unsigned long long m = __ballot(unstable);
-    if ((m != 0ull || guarded_in_wave != 0) && __lane_id() == 0) {
-        if (m != 0ull) {
+    const unsigned long long m = __ballot(bad_node != kNoNode);
+    if (m != 0ull) {
+        int v = bad_node;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+        if (__lane_id() == 0) {
             const int64_t s = step + (step_base ? *step_base : 0);
             atomicOr(&st->flags, 1u);
-            atomicMin((unsigned long long *)&st->first_step, (unsigned long long)s);
+            atomicMin((unsigned long long *)&st->first, (unsigned long long)event_key(s, v));
         }
-        if (guarded_in_wave != 0) {
-            atomicOr(&st->flags, 2u);
-            atomicAdd((unsigned long long *)&st->guarded, (unsigned long long)guarded_in_wave);
-        }
+    }
+    if (guarded_in_wave != 0 && __lane_id() == 0) {
+        atomicOr(&st->flags, 2u);
+        atomicAdd((unsigned long long *)&st->guarded, (unsigned long long)guarded_in_wave);
     }
 }
 
@@ -460,7 +478,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
     const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(typename Form<ST>::T));
     C ref[9];
     ref9<C>(C(in.rho0), ref);
-    bool bad = false;
+    int bad = kNoNode;
     int guarded = 0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -482,7 +500,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
             for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         }
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
-        bad = bad || (xin && (fl & 1));
+        if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
         if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
@@ -526,7 +544,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
     const bool vec = (nx % V) == 0;
     C ref[9];
     ref9<C>(C(in.rho0), ref);
-    bool bad = false;
+    int bad = kNoNode;
     int guarded = 0;
     for (int r = 0; r < RY; ++r) {
         const int y = ty * RY + r;  // uniform across the block
@@ -572,7 +590,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&win[q][t + V - cx9(q)], ref[q], a.fp16_iscale);
         __syncthreads();  // the windows are restaged for the next row
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
-        bad = bad || (xin && (fl & 1));
+        if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
         if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
@@ -601,7 +619,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(T));
     C ref[9];
     ref9<C>(C(in.rho0), ref);
-    bool bad = false;
+    int bad = kNoNode;
     int guarded = 0;
     T raw[9];
     {
@@ -624,7 +642,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
             continue;
         }
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
-        bad = bad || (xin && (fl & 1));
+        if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
         if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
@@ -680,7 +698,7 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     if (valid)
         push9_inst<ST, (NT & 2) != 0>(uniform_addr(dst + in.offset), P, (uint32_t)node * E, f, ref, a.fp16_scale);
     const int guarded = __popcll(__ballot(valid && (fl & 2)));
-    report(a.status + i, valid && (fl & 1), guarded, a.step, a.step_base);
+    report(a.status + i, valid && (fl & 1) ? node : kNoNode, guarded, a.step, a.step_base);
 }
 
 // --------------------------------------------------------------------------
@@ -715,7 +733,8 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     const float inx = __builtin_amdgcn_rcpf((float)nx);
-    int64_t first_bad = INT64_MAX;
+    const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
+    uint64_t first_bad = ~0ull;
     int64_t guarded = 0;
     for (int k = 0; k < nsteps; ++k) {
         const T *sin = (k & 1) ? L1 : L0;
@@ -729,7 +748,7 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
             C f[9];
             pull9<ST>(sin, nodes, x, y, nx, n, ref, a.fp16_iscale, f);
             const int fl = node9<ST, CO>(f, role9(x, y, nx, ny, a.bc), in);
-            if ((fl & 1) && first_bad == INT64_MAX) first_bad = k;
+            if ((fl & 1) && first_bad == ~0ull) first_bad = event_key(s0 + k, node);  // first step, smallest node of this thread
             guarded += (fl >> 1) & 1;
             push9<ST>(sout, nodes, node, f, ref, a.fp16_scale);
         }
@@ -743,10 +762,9 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
     }
     // Status: rare events, one atomic per reporting lane.
     DevStatus *st = a.status + i;
-    if (first_bad != INT64_MAX) {
-        const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
+    if (first_bad != ~0ull) {
         atomicOr(&st->flags, 1u);
-        atomicMin((unsigned long long *)&st->first_step, (unsigned long long)(s0 + first_bad));
+        atomicMin((unsigned long long *)&st->first, (unsigned long long)first_bad);
     }
     if (guarded != 0) {
         atomicOr(&st->flags, 2u);
@@ -852,9 +870,9 @@ __device__ __forceinline__ void st8(T *p, const T (&v)[8])
 // from the left, plane 2 from the right) take one scalar load each, with the
 // same wrap/clamp rule as the one-node form, so results are bitwise equal to
 // it.  Nodes beyond nx in the last group are computed but neither stored nor
-// counted.  Returns true if a valid node was unstable.
+// counted.  Returns the smallest unstable valid node of the group, or kNoNode.
 template <int ST, int NT = 0>
-__device__ __forceinline__ bool step3_group8(const typename Form<ST>::T *__restrict__ s,
+__device__ __forceinline__ int step3_group8(const typename Form<ST>::T *__restrict__ s,
                                              typename Form<ST>::T *__restrict__ d, int64_t P, int x0, int nx,
                                              int bc, typename Form<ST>::C omega, typename Form<ST>::C rho0,
                                              const StepArgs &a)
@@ -873,7 +891,7 @@ __device__ __forceinline__ bool step3_group8(const typename Form<ST>::T *__restr
     const int xp = xl < nx - 1 ? xl + 1 : (wrap ? 0 : nx - 1);
     const T s1 = ldraw<T, NL>(s + P + xm), s2 = ldraw<T, NL>(s + 2 * P + xp);
     const C r0 = C(2.0 / 3.0) * rho0, r1 = C(1.0 / 6.0) * rho0;
-    bool bad = false;
+    int bad = kNoNode;
     // Results go back into v0 and v2 in place (node j reads only v0[j] and
     // v2[j+1], not yet overwritten when walking upwards) but into o1 for
     // plane 1, whose node j reads v1[j-1].
@@ -888,7 +906,7 @@ __device__ __forceinline__ bool step3_group8(const typename Form<ST>::T *__restr
         C fm = load<ST>(&rm, r1, a.fp16_iscale);
         const int role = (bc != BC_PERIODIC && (x == 0 || x == nx - 1)) ? R_WALL : R_FLUID;
         const int fl = node3<C>(f0, fp, fm, role, omega);
-        bad = bad || (j <= jl && fl);
+        if (bad == kNoNode && j <= jl && fl) bad = x;
         if constexpr (ST == ST_F16DEV) {
             v0[j] = enc16(f0, r0, a.fp16_scale);
             o1[j] = enc16(fp, r1, a.fp16_scale);
@@ -920,7 +938,7 @@ __global__ __launch_bounds__(BX) void k_d1q3_v8(const typename Form<ST>::T *__re
     using C = typename Form<ST>::C;
     const Inst &in = a.one;
     const int x0 = (blockIdx.x * BX + (int)threadIdx.x) * 8;
-    bool bad = false;
+    int bad = kNoNode;
     if (x0 < in.nx) bad = step3_group8<ST, NT>(src, dst, in.plane, x0, in.nx, a.bc, C(in.omega), C(in.rho0), a);
     report(a.status, bad, 0, a.step, a.step_base);
 }
@@ -935,7 +953,7 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch_v8(const typename Form<ST>::
     const int i = a.tile_inst[t];
     const Inst &in = a.inst[i];
     const int x0 = a.tile_first[t] + (int)threadIdx.x * 8;
-    bool bad = false;
+    int bad = kNoNode;
     if (x0 < in.nx)
         bad = step3_group8<ST, NT>(src + in.offset, dst + in.offset, in.plane, x0, in.nx, a.bc, C(in.omega),
                                    C(in.rho0), a);
@@ -949,14 +967,14 @@ __global__ __launch_bounds__(BX) void k_d1q3(const typename Form<ST>::T *__restr
     using C = typename Form<ST>::C;
     const Inst &in = a.one;
     const int nx = in.nx;
-    bool bad = false;
+    int bad = kNoNode;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int x = (blockIdx.x * NPT + k) * BX + (int)threadIdx.x;
         const bool valid = x < nx;
         const int fl = step3_node<ST, NT>(src, dst, in.plane, valid ? x : nx - 1, nx, a.bc, C(in.omega),
                                       C(in.rho0), a, valid);
-        bad = bad || (valid && fl);
+        if (valid && fl) bad = min(bad, x);
     }
     report(a.status, bad, 0, a.step, a.step_base);
 }
@@ -971,14 +989,14 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *
     const int i = a.tile_inst[t];
     const Inst &in = a.inst[i];
     const int nx = in.nx;
-    bool bad = false;
+    int bad = kNoNode;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int x = a.tile_first[t] + k * BLK + (int)threadIdx.x;
         const bool valid = x < nx;
         const int fl = step3_node<ST, NT>(src + in.offset, dst + in.offset, in.plane, valid ? x : nx - 1, nx, a.bc,
                                       C(in.omega), C(in.rho0), a, valid);
-        bad = bad || (valid && fl);
+        if (valid && fl) bad = min(bad, x);
     }
     report(a.status + i, bad, 0, a.step, a.step_base);
 }
@@ -1099,7 +1117,7 @@ __global__ void k_clear_status(DevStatus *st, int n)
     if (i < n) {
         st[i].flags = 0;
         st[i].pad = 0;
-        st[i].first_step = INT64_MAX;
+        st[i].first = ~0ull;
         st[i].guarded = 0;
     }
 }

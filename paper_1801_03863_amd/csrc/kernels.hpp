@@ -15,7 +15,7 @@ enum Bc { BC_PERIODIC = 0, BC_TUBE = 1, BC_CAVITY = 2, BC_BOX = 3 };
 struct DevStatus {
     uint32_t flags;
     int32_t pad;
-    int64_t first_step;  // INT64_MAX until the first instability
+    uint64_t first;  // (step << 32) | node of the first unstable node; all ones until then
     int64_t guarded;
 };
 

@@ -830,7 +830,9 @@ int lbm_status_batch(lbm_ctx_t *c, lbm_status_t *out, int32_t n)
     for (int i = 0; i < n; ++i) {
         out[i].flags = h[i].flags;
         out[i].reserved = 0;
-        out[i].first_step = h[i].first_step == INT64_MAX ? -1 : h[i].first_step;
+        const bool none = h[i].first == ~0ull;
+        out[i].first_step = none ? -1 : (int64_t)(h[i].first >> 32);
+        out[i].first_node = none ? -1 : (int64_t)(h[i].first & 0xffffffffull);
         out[i].guarded = h[i].guarded;
     }
     return LBM_OK;
@@ -842,11 +844,19 @@ int lbm_status(lbm_ctx_t *c, lbm_status_t *out)
     std::vector<lbm_status_t> all(c->n);
     int rc = lbm_status_batch(c, all.data(), c->n);
     if (rc) return rc;
-    lbm_status_t s{0, 0, -1, 0};
-    for (const auto &x : all) {
+    // Over a batch: the earliest step, and at that step the smallest node in
+    // the instances' concatenated node order.
+    lbm_status_t s{0, 0, -1, -1, 0};
+    for (int i = 0; i < c->n; ++i) {
+        const lbm_status_t &x = all[i];
         s.flags |= x.flags;
         s.guarded += x.guarded;
-        if (x.first_step >= 0 && (s.first_step < 0 || x.first_step < s.first_step)) s.first_step = x.first_step;
+        if (x.first_step < 0) continue;
+        const int64_t node = c->node_prefix[i] + x.first_node;
+        if (s.first_step < 0 || x.first_step < s.first_step || (x.first_step == s.first_step && node < s.first_node)) {
+            s.first_step = x.first_step;
+            s.first_node = node;
+        }
     }
     *out = s;
     return LBM_OK;

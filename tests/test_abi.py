@@ -38,7 +38,9 @@ def test_library_exports_every_declared_symbol(B):
 
 def test_struct_layouts(B):
     assert ctypes.sizeof(B.lbm_params_t) == 64
-    assert ctypes.sizeof(B.lbm_status_t) == 24
+    assert ctypes.sizeof(B.lbm_status_t) == 32
+    assert (B.lbm_status_t.first_step.offset, B.lbm_status_t.first_node.offset, B.lbm_status_t.guarded.offset) == \
+        (8, 16, 24)
 
 
 @pytest.mark.parametrize("bad", [

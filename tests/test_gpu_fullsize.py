@@ -191,6 +191,7 @@ def test_batched_tubes(precision):
             assert sts[k]["unstable"], (k, n)
             if precision == "fp64":
                 assert sts[k]["first_step"] == o["first_step"], (k, n)
+                assert sts[k]["first_node"] == o["first_node"], (k, n)
             off += n
             continue
         fl = fluid_mask("d1q3", "tube", n, 1)
@@ -324,6 +325,7 @@ def test_lds_resident_persistent_batch_is_bitwise(precision, steps):
     assert np.array_equal(F1, F2, equal_nan=True)
     for a_, b_ in zip(S1, S2):
         assert a_["unstable"] == b_["unstable"] and a_["first_step"] == b_["first_step"]
+        assert a_["first_node"] == b_["first_node"]
         assert a_["guarded"] == b_["guarded"]
 
 
@@ -358,6 +360,7 @@ def test_full_cavity_batch_5000_steps_against_oracle(tmp_path):
         assert sts[i]["unstable"] == o["unstable"], (i, n, re)
         if o["unstable"]:
             assert sts[i]["first_step"] == o["first_step"], (i, n, re)
+            assert sts[i]["first_node"] == o["first_node"], (i, n, re)
             continue
         m = n * n
         g = {"rho": R[offs[i]:offs[i] + m].reshape(n, n), "ux": U[offs[i]:offs[i] + m].reshape(n, n),
@@ -397,6 +400,7 @@ def test_full_tube_batch_1000_steps_against_oracle(tmp_path):
         assert sts[i]["unstable"] == o["unstable"], (i, n)
         if o["unstable"]:
             assert sts[i]["first_step"] == o["first_step"], (i, n)
+            assert sts[i]["first_node"] == o["first_node"], (i, n)
             continue
         fl = fluid_mask("d1q3", "tube", n, 1)
         er = np.max(np.abs(R[offs[i]:offs[i] + n] - o["rho"])[fl]) / np.max(np.abs(o["rho"][fl]))

@@ -114,6 +114,21 @@ def test_unstable_flag_and_first_step_match_oracle():
     o = orc_run("d2q9", "srt", "cavity", n, n, 0.5001, np.ones((n, n)), z, z, steps=300, u_lid=0.4)
     assert o["unstable"] and g["status"]["unstable"]
     assert g["status"]["first_step"] == o["first_step"]
+    assert g["status"]["first_node"] == o["first_node"] >= 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_newton64", "fp32", "fp16dev"])
+def test_first_unstable_node_is_the_perturbed_one(precision):
+    # As in the oracle pin: only node (5, 3) starts with negative start-point
+    # populations, so every form reports step 0 at node 3*nx + 5.
+    nx, ny = 300, 70  # several tiles per row, several rows per launch shape
+    rho = np.ones((ny, nx))
+    ux = np.zeros((ny, nx))
+    ux[3, 5] = 0.9
+    z = np.zeros((ny, nx))
+    g = gpu_run("d2q9", "minxent4", "periodic", precision, nx, ny, 0.8, rho, ux, z, steps=3)
+    assert g["status"]["unstable"] and g["status"]["first_step"] == 0
+    assert g["status"]["first_node"] == 3 * nx + 5
 
 
 def test_guarded_nodes_counted_like_oracle():

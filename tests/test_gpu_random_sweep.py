@@ -58,6 +58,7 @@ def test_random_configuration_against_oracle(k):
     assert g["status"]["guarded"] == o["guarded"], c
     if o["unstable"]:
         assert g["status"]["first_step"] == o["first_step"], c
+        assert g["status"]["first_node"] == o["first_node"], c
         return
     errs = field_errors(g, o, fluid_mask(c["lattice"], c["bc"], c["nx"], c["ny"]), fields)
     print("variant", variant, {f: ("%.1e" % e[0], "%.1e" % e[1]) for f, e in errs.items()}, flush=True)

@@ -527,6 +527,26 @@ def test_unstable_flag_on_negative_populations(orc):
     assert r["unstable"] and r["first_step"] >= 0
 
 
+def test_first_unstable_node_is_the_perturbed_one(orc):
+    # Every node at rest except (5, 3), whose velocity 0.9 gives its start
+    # point negative populations: it alone can fail the stability test in the
+    # first collision, so the first event is step 0 at node 3*8 + 5.
+    nx, ny = 8, 6
+    rho = np.ones((ny, nx))
+    ux = np.zeros((ny, nx))
+    ux[3, 5] = 0.9
+    r = orc.run(orc.D2Q9, orc.MINXENT4, orc.BC_PERIODIC, nx, ny, 0.8, rho, ux, np.zeros((ny, nx)), steps=3)
+    assert r["unstable"] and r["first_step"] == 0 and r["first_node"] == 3 * nx + 5
+    # The same node seen through a window that starts at (2, 1).
+    w = orc.run(orc.D2Q9, orc.MINXENT4, orc.BC_PERIODIC, nx, ny, 0.8, rho[1:5, 2:8], ux[1:5, 2:8],
+                np.zeros((4, 6)), steps=1, window=(2, 1, 6, 4))
+    assert w["first_step"] == 0 and w["first_node"] == 3 * nx + 5
+    # A stable run reports no node.
+    q = orc.run(orc.D2Q9, orc.MINXENT4, orc.BC_PERIODIC, nx, ny, 0.8, rho, np.zeros((ny, nx)),
+                np.zeros((ny, nx)), steps=3)
+    assert not q["unstable"] and q["first_step"] == -1 and q["first_node"] == -1
+
+
 def test_rejects_tau_at_or_below_one_half(orc):
     with pytest.raises(ValueError):
         orc.run(orc.D1Q3, orc.SRT, orc.BC_TUBE, 10, 1, 0.5, np.ones(10), np.zeros(10), steps=1)
