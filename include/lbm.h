@@ -143,6 +143,15 @@ int lbm_init_batch(const lbm_params_t *p, int32_t n, const double *rho, const do
  * context's stream and return without waiting.  nsteps >= 0. */
 int lbm_step(lbm_ctx_t *ctx, int64_t nsteps);
 
+/* Per-instance step counts of a batch: instance i takes no step once the
+ * context has completed stop_steps[i] steps (counted from its creation, as
+ * lbm_info reports them); from then on its state is carried over unchanged
+ * and lbm_moments returns it as it was after that step.  A negative entry,
+ * or stop_steps == NULL, removes the limits.  n must equal the number of
+ * instances.  Works with graph replay and the LDS-resident shape.
+ * LBM_EINVAL for a single-lattice context.  Synchronises. */
+int lbm_set_batch_steps(lbm_ctx_t *ctx, const int64_t *stop_steps, int32_t n);
+
 /* Replay time steps from a captured HIP graph of `chunk` steps (chunk >= 1;
  * 0 turns graph replay off).  lbm_step() then enqueues nsteps / chunk graph
  * launches plus the remainder as plain launches.  Results are bitwise equal

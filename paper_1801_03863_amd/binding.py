@@ -93,6 +93,7 @@ _sig("lbm_set_variant", ctypes.c_int, [_V, ctypes.c_int32])
 _sig("lbm_variant_count", ctypes.c_int, [_V])
 _sig("lbm_variant_name", ctypes.c_char_p, [_V, ctypes.c_int32])
 _sig("lbm_set_plane_pad", ctypes.c_int, [_V, ctypes.c_int32])
+_sig("lbm_set_batch_steps", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.c_int32])
 _sig("lbm_get_layout", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)])
 _sig("lbm_moments", ctypes.c_int, [_V, _D, _D, _D])
 _sig("lbm_get_populations", ctypes.c_int, [_V, _D])
@@ -218,6 +219,15 @@ def lbm_set_variant(ctx, v):
 
 def lbm_variant_count(ctx):
     return _lib.lbm_variant_count(ctx)
+
+
+def lbm_set_batch_steps(ctx, stop_steps):
+    """Per-instance step limits of a batch (None removes them)."""
+    if stop_steps is None:
+        _check(_lib.lbm_set_batch_steps(ctx, None, 0), "lbm_set_batch_steps")
+        return
+    a = np.ascontiguousarray(np.asarray(stop_steps, dtype=np.int64))
+    _check(_lib.lbm_set_batch_steps(ctx, a.ctypes.data_as(ctypes.POINTER(_I64)), len(a)), "lbm_set_batch_steps")
 
 
 def lbm_set_plane_pad(ctx, pad_bytes):

@@ -424,6 +424,20 @@ __device__ __forceinline__ void report(DevStatus *st, int bad_node, int guarded_
     }
 }
 
+// Batched instances with a step limit: once the step index reaches the
+// instance's `stop`, its launches carry the state over unchanged (the two
+// buffers alternate for the whole batch).
+__device__ __forceinline__ bool instance_stopped(const StepArgs &a, const Inst &in)
+{
+    return in.stop <= a.step + (a.step_base ? *a.step_base : 0);
+}
+
+template <class T>
+__device__ __forceinline__ void carry_node(const T *__restrict__ s, T *__restrict__ d, int64_t P, int planes, int node)
+{
+    for (int q = 0; q < planes; ++q) d[q * P + node] = s[q * P + node];
+}
+
 // Map block b of a grid of nb blocks so that the blocks the hardware sends to
 // one XCD (b, b+8, b+16, ...) cover a contiguous range of tiles.
 __device__ __forceinline__ int xcd_remap(int b, int nb)
@@ -669,6 +683,10 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     const int nodes = nx * ny;
     int node = a.tile_first[t] + (int)threadIdx.x;
     const bool valid = node < nodes;
+    if (instance_stopped(a, in)) {  // uniform across the block
+        if (valid) carry_node(src + in.offset, dst + in.offset, P, 9, node);
+        return;
+    }
     if (!valid) node = nodes - 1;
     // node -> (x, y): float estimate, exact after one correction (node < 2^24).
     int y = (int)((float)node * __builtin_amdgcn_rcpf((float)nx));
@@ -736,7 +754,11 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
     const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
     uint64_t first_bad = ~0ull;
     int64_t guarded = 0;
+    // Steps this instance takes in this launch (its step limit may end them
+    // early; the break below is uniform across the block).
+    const int kdone = (int)max((int64_t)0, min((int64_t)nsteps, in.stop - s0));
     for (int k = 0; k < nsteps; ++k) {
+        if (k >= kdone) break;
         const T *sin = (k & 1) ? L1 : L0;
         T *sout = (k & 1) ? L0 : L1;
         for (int node = threadIdx.x; node < nodes; node += blockDim.x) {
@@ -754,7 +776,7 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
         }
         __syncthreads();
     }
-    const T *fin = (nsteps & 1) ? L1 : L0;
+    const T *fin = (kdone & 1) ? L1 : L0;
     T *o = dst + in.offset;
     for (int idx = threadIdx.x; idx < 9 * nodes; idx += blockDim.x) {
         const int q = idx / nodes, j = idx - q * nodes;
@@ -953,6 +975,11 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch_v8(const typename Form<ST>::
     const int i = a.tile_inst[t];
     const Inst &in = a.inst[i];
     const int x0 = a.tile_first[t] + (int)threadIdx.x * 8;
+    if (instance_stopped(a, in)) {  // uniform across the block
+        for (int j = 0; j < 8 && x0 + j < in.nx; ++j)
+            carry_node(src + in.offset, dst + in.offset, in.plane, 3, x0 + j);
+        return;
+    }
     int bad = kNoNode;
     if (x0 < in.nx)
         bad = step3_group8<ST, NT>(src + in.offset, dst + in.offset, in.plane, x0, in.nx, a.bc, C(in.omega),
@@ -989,6 +1016,13 @@ __global__ __launch_bounds__(BLK) void k_d1q3_batch(const typename Form<ST>::T *
     const int i = a.tile_inst[t];
     const Inst &in = a.inst[i];
     const int nx = in.nx;
+    if (instance_stopped(a, in)) {  // uniform across the block
+        for (int k = 0; k < NPT; ++k) {
+            const int x = a.tile_first[t] + k * BLK + (int)threadIdx.x;
+            if (x < nx) carry_node(src + in.offset, dst + in.offset, in.plane, 3, x);
+        }
+        return;
+    }
     int bad = kNoNode;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {

@@ -31,6 +31,7 @@ struct Inst {
     double u_lid;
     double rho0;
     double lid[9];   // equilibrium of (rho0, (u_lid, 0))
+    int64_t stop;    // batched: the instance takes no step from this step index on
 };
 
 // Everything a step launch needs besides the buffers.

@@ -173,6 +173,7 @@ int layout(const lbm_params_t *p, int32_t n, int batch, int b, std::vector<Inst>
         in.nx = q.nx;
         in.ny = q.lattice == LBM_D1Q3 ? 1 : q.ny;
         in.offset = off;
+        in.stop = INT64_MAX;
         in.plane = round_up((int64_t)in.nx * in.ny, kAlignElems);
         int64_t room = in.plane;  // elements reserved per plane
         if (paddable(q, batch)) {
@@ -626,6 +627,21 @@ int lbm_set_plane_pad(lbm_ctx_t *c, int32_t pad_bytes)
     if (pad_bytes < 0 || pad_bytes > kPadMaxBytes || pad_bytes % 256 != 0)
         return fail(LBM_EINVAL, "plane pad must be a multiple of 256 bytes in [0, 8192]");
     return set_pad(c, pad_bytes);
+}
+
+int lbm_set_batch_steps(lbm_ctx_t *c, const int64_t *stop_steps, int32_t n)
+{
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (!c->batch) return fail(LBM_EINVAL, "step limits apply to batched contexts");
+    if (stop_steps && n != c->n) return fail(LBM_EINVAL, "need one step limit per instance");
+    if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    else HIPCHK(hipDeviceSynchronize());
+    for (int i = 0; i < c->n; ++i) {
+        const int64_t v = stop_steps ? stop_steps[i] : -1;
+        c->inst[i].stop = v < 0 ? INT64_MAX : v;
+    }
+    HIPCHK(hipMemcpy(c->d_inst, c->inst.data(), sizeof(Inst) * c->n, hipMemcpyHostToDevice));
+    return LBM_OK;
 }
 
 int lbm_get_layout(const lbm_ctx_t *c, int64_t *plane_stride, int32_t *pad_bytes)

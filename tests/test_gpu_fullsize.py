@@ -438,3 +438,85 @@ def test_benchmark_cavity_fp64_60_steps_sampled(tmp_path):
     worst["u"] /= umax
     print("fp64 60 steps", worst, "umax", umax, flush=True)
     assert worst["rho"] <= 1e-12 and worst["u"] <= 1e-12
+
+
+def _limits_case(b, lattice, sizes, limits, variants, graph):
+    """Batch with per-instance step limits, stepped 5 + 7 times, against the
+    oracle run of each instance for min(limit, 12) steps."""
+    rng = np.random.default_rng(77)
+    params, fields = [], []
+    for n in sizes:
+        if lattice == "d2q9":
+            r = 1.0 + 0.02 * rng.uniform(-1, 1, (n, n))
+            u = 0.02 * rng.uniform(-1, 1, (n, n))
+            v = 0.02 * rng.uniform(-1, 1, (n, n))
+            params.append(b.make_params("d2q9", "minxent4", "cavity", "fp64", n, n, 0.6, 0.0, 0.05, 1.0))
+        else:
+            r = 1.0 + 0.2 * rng.uniform(-1, 1, n)
+            u = 0.05 * rng.uniform(-1, 1, n)
+            v = None
+            params.append(b.make_params("d1q3", "srt", "tube", "fp64", n, 1, 0.7, 0.0, 0.0, 1.0))
+        fields.append((r, u, v))
+    cat = lambda k: np.concatenate([f[k].ravel() for f in fields]) if fields[0][k] is not None else None
+    for variant in variants:
+        ctx = b.lbm_init_batch(params, cat(0), cat(1), cat(2))
+        try:
+            if variant == "lds":
+                v = b.lbm_variant_count(ctx) - 1
+                assert "LDS" in b.lbm_variant_name(ctx, v)
+            else:
+                v = variant
+            b.lbm_set_variant(ctx, v)
+            if graph:
+                b.lbm_set_graph_chunk(ctx, graph)
+            b.lbm_set_batch_steps(ctx, limits)
+            b.lbm_step(ctx, 5)
+            b.lbm_step(ctx, 7)
+            R, U, V = b.lbm_moments(ctx)
+            sts = b.lbm_status_batch(ctx, len(sizes))
+        finally:
+            b.lbm_free(ctx)
+        off = 0
+        for k, n in enumerate(sizes):
+            m = n * n if lattice == "d2q9" else n
+            steps = 12 if limits[k] < 0 else min(limits[k], 12)
+            ny = n if lattice == "d2q9" else 1
+            shape = (n, n) if lattice == "d2q9" else (n,)
+            o = orc_run(lattice, "minxent4" if lattice == "d2q9" else "srt", "cavity" if lattice == "d2q9" else "tube",
+                        n, ny, 0.6 if lattice == "d2q9" else 0.7, fields[k][0], fields[k][1], fields[k][2],
+                        steps=steps, u_lid=0.05 if lattice == "d2q9" else 0.0)
+            fl = fluid_mask(lattice, "cavity" if lattice == "d2q9" else "tube", n, ny)
+            for name, G in (("rho", R), ("ux", U)):
+                g = G[off:off + m].reshape(shape)
+                e = np.max(np.abs(g - o[name])[fl]) / np.max(np.abs(o[name][fl]))
+                assert e <= 1e-12, (variant, k, n, limits[k], name, e)
+            assert sts[k]["unstable"] == o["unstable"]
+            off += m
+
+
+@pytest.mark.parametrize("graph", [0, 4])
+def test_batch_step_limits_d2q9(graph):
+    b = B()
+    # launch shapes of the tiled batch kernel, and (small instances) the
+    # LDS-resident persistent shape
+    _limits_case(b, "d2q9", [20, 33, 47, 64, 90], [3, 10, 0, 7, -1], [0, 4, 5], graph)
+    _limits_case(b, "d2q9", [12, 20, 25, 30], [3, -1, 0, 11], [0, "lds"], graph)
+
+
+def test_batch_step_limits_d1q3():
+    b = B()
+    _limits_case(b, "d1q3", [100, 1000, 2500, 37], [3, 10, 0, -1], [0, 1, 5, 8], 0)
+    ctx = b.lbm_init_batch([b.make_params("d1q3", "srt", "tube", "fp64", 50, 1, 0.7)] * 2,
+                           np.ones(100), np.zeros(100), None)
+    try:
+        with pytest.raises(b.LbmError):
+            b.lbm_set_batch_steps(ctx, [1, 2, 3])  # one per instance
+        b.lbm_set_batch_steps(ctx, None)
+    finally:
+        b.lbm_free(ctx)
+    single = b.lbm_init(b.make_params("d1q3", "srt", "tube", "fp64", 50, 1, 0.7), np.ones(50), np.zeros(50), None)
+    try:
+        with pytest.raises(b.LbmError):
+            b.lbm_set_batch_steps(single, [1])  # batches only
+    finally:
+        b.lbm_free(single)
