@@ -8,8 +8,11 @@ computed in FP64 (moments, logarithms, Newton step, correction).  The same
 steps are also timed for the plain FP64 form; the headline form's field error
 against it is reported.
 
-One step = one fused launch over all 16.8 M nodes.  Inputs are resident in
-HBM before timing starts.  MLUPS = nodes * timed steps / seconds / 1e6.
+One step = one pass of the fused update over all 16.8 M nodes; the launch
+shape the autotuner picks takes one or two steps per launch (the two-step
+shapes keep the intermediate step in on-chip memory; results are bitwise the
+same).  Inputs are resident in HBM before timing starts.  MLUPS = nodes *
+timed steps / seconds / 1e6.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 Prints one JSON line.
@@ -26,7 +29,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
+# second (one wave64 VALU instruction is 64 lane-operations issued over four
+# cycles); equal to the FP64 vector FMA rate, 78.6 TFLOP/s / 2.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_d2q9_fp32n64_cavity4096.txt")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_d2q9_cavity4096.txt")
+# The single-step shape quoted beside a two-step headline: 256 x 1 tiles,
+# non-temporal loads of the unshifted planes and non-temporal stores, an
+# 8-wave register budget, raised issue priority while the loads issue.
+SINGLE_STEP_SHAPE = 25
 
 
 def kernel_source_digest():
@@ -50,6 +62,20 @@ def read_traffic(digest):
     return float(m_b.group(1))
 
 
+def read_valu(digest):
+    """VALU lane-operations per node and step of the headline kernel from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source."""
+    if not os.path.exists(PROFILE_VALU):
+        return None
+    txt = open(PROFILE_VALU).read()
+    m_src = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_v = re.search(r"headline_valu_per_node_step:\s*([0-9.eE+]+)", txt)
+    if not m_src or not m_v or m_src.group(1) != digest:
+        return None
+    return float(m_v.group(1))
+
+
 def fluid_errors(a, b, n):
     import numpy as np
     out = {}
@@ -62,12 +88,18 @@ def fluid_errors(a, b, n):
     return out
 
 
-def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_cache):
+def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_cache, force_variant=None):
+    """Autotune (or read the cache), optionally replace the chosen shape by
+    force_variant (the tuned plane pad stays), then time `steps` steps."""
     p = B.make_params("d2q9", "minxent4", "cavity", precision, n, n, tau, 0.0, u_lid, 1.0)
     ws = torch.empty(B.lbm_workspace_bytes(p), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     ctx = B.lbm_init(p, *fields, workspace=ws, stream=stream)
     variant = B.lbm_autotune(ctx, tune_cache)
+    if force_variant is not None:
+        variant = force_variant
+        B.lbm_set_variant(ctx, variant)
+    spl = B.lbm_variant_steps(ctx, variant)
     B.lbm_step(ctx, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -88,7 +120,7 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
         shape += ", plane pad %d B" % pad
     B.lbm_free(ctx)
     del ws
-    return {"wall_s": wall, "event_ms": ev_ms, "variant": shape,
+    return {"wall_s": wall, "event_ms": ev_ms, "variant": shape, "steps_per_launch": spl,
             "nodes": info["nodes"], "bytes_per_step": info["bytes_per_step"],
             "fields": {"rho": r, "ux": u, "uy": v}, "status": st}
 
@@ -123,14 +155,18 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, gr
     del ws
     return {"wall_s": wall, "event_ms": e0.elapsed_time(e1), "variant": shape, "nodes": info["nodes"],
             "bytes_per_step": info["bytes_per_step"], "fields": {"rho": r, "ux": u, "uy": v}, "status": st,
-            "per_instance": per}
+            "per_instance": per, "steps_per_launch": 1}
 
 
 def rate(res, steps):
+    """MLUPS, and the algorithmic HBM rate of one launch: every stored
+    population read once and written once per launch, whether the launch
+    takes one step or two."""
     mlups = res["nodes"] * steps / res["wall_s"] / 1e6
-    gbs = res["bytes_per_step"] / (res["event_ms"] / steps * 1e-3) / 1e9
+    spl = res["steps_per_launch"]
+    gbs = res["bytes_per_step"] / (res["event_ms"] / steps * spl * 1e-3) / 1e9
     return {"mlups": round(mlups, 1), "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "launch_shape": res["variant"], "unstable": res["status"]["unstable"]}
+            "steps_per_launch": spl, "launch_shape": res["variant"], "unstable": res["status"]["unstable"]}
 
 
 def rel_errors(a, b, mask):
@@ -340,9 +376,11 @@ def main():
     head = time_form(B, torch, "fp32_newton64", n, tau, cfg["u_lid"], fields, args.steps, args.warmup,
                      args.tune_cache)
     nodes = head["nodes"]
-    ms_event = head["event_ms"] / args.steps
+    spl = head["steps_per_launch"]
+    ms_event = head["event_ms"] / args.steps  # per step
+    ms_launch = ms_event * spl                # the timed steps are a whole number of launches
     value = nodes * args.steps / head["wall_s"] / 1e6
-    achieved = head["bytes_per_step"] / (ms_event * 1e-3) / 1e9
+    hbm_achieved = head["bytes_per_step"] / (ms_launch * 1e-3) / 1e9
 
     out = {
         "metric": "MLUPS and % of HBM roofline, FP64 vs FP32/batched at stated field error",
@@ -363,17 +401,34 @@ def main():
     }
     digest = kernel_source_digest()
     traffic = read_traffic(digest)
-    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "algorithmic_bytes_per_launch": head["bytes_per_step"],
-                       "kernel_ms_per_launch": round(ms_event, 5)}
+    hbm = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": head["bytes_per_step"], "kernel_ms_per_launch": round(ms_launch, 5),
+           "steps_per_launch": spl}
+    if spl == 1:
+        out["roofline"] = hbm
+    else:
+        # Two steps per launch halve the HBM bytes per step; the kernel is then
+        # bound by VALU issue.  Lane-operations per node and step come from
+        # the committed counter summary of the same kernel sources.
+        valu = read_valu(digest)
+        alu = None if valu is None else valu * nodes * spl / (ms_launch * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": None if alu is None else round(alu, 3),
+                           "peak": round(VALU_PEAK_TOPS, 3), "unit": "T VALU lane-ops/s",
+                           "frac": None if alu is None else round(alu / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                           "valu_lane_ops_per_node_step": valu, "kernel_ms_per_launch": round(ms_launch, 5),
+                           "steps_per_launch": spl, "hbm": hbm}
     out["status"] = head["status"]
+    # The best single-step shape on the same lattice, the fused kernel as a
+    # pure HBM stream (one read and one write of every population per step).
+    single = time_form(B, torch, "fp32_newton64", n, tau, cfg["u_lid"], fields, args.extra_steps, args.warmup,
+                       args.tune_cache, force_variant=SINGLE_STEP_SHAPE)
+    out["single_step_fused_kernel"] = rate(single, args.extra_steps)
     if not args.no_fp64:
         ref = time_form(B, torch, "fp64", n, tau, cfg["u_lid"], fields, args.steps, args.warmup, args.tune_cache)
         fp64_mlups = nodes * args.steps / ref["wall_s"] / 1e6
-        out["fp64"] = {"mlups": round(fp64_mlups, 1),
-                       "achieved_gbs": round(ref["bytes_per_step"] / (ref["event_ms"] / args.steps * 1e-3) / 1e9, 1),
-                       "speedup_of_headline": round(value / fp64_mlups, 3)}
+        out["fp64"] = rate(ref, args.steps)
+        out["fp64"]["speedup_of_headline"] = round(value / fp64_mlups, 3)
         out["field_error_vs_fp64"] = fluid_errors(head["fields"], ref["fields"], n)
     if not args.no_extra:
         ref32 = time_form(B, torch, "fp32", n, tau, cfg["u_lid"], fields, args.extra_steps, args.warmup,

@@ -160,7 +160,7 @@ int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
 
 /* Time the candidate launch shapes of the fused kernel on this context's own
  * buffers (the state is left unchanged) and keep the fastest: every shape
- * is timed, then the three fastest again with longer trials taken in turn.
+ * is timed, then the five fastest again with longer trials taken in turn.
  * Candidates produce bitwise identical results.  If cache_path is not NULL
  * the choice is read from / appended to that text file, keyed by a hash of
  * the kernel sources, device, lattice, precision, collision, boundary and
@@ -196,6 +196,15 @@ int lbm_set_variant(lbm_ctx_t *ctx, int32_t variant);
 int lbm_variant_count(const lbm_ctx_t *ctx);
 const char *lbm_variant_name(const lbm_ctx_t *ctx, int32_t variant);
 
+/* Steps one launch of a shape takes: 1, or 2 for the temporally blocked
+ * shapes of a single D2Q9 lattice (MinxEnt4), which compute one step into
+ * on-chip memory and the next from there, so that HBM sees one read and one
+ * write of every population per two steps.  Their results are bitwise equal
+ * to single steps; lbm_step() runs an odd count's last step, and a graph
+ * chunk's, on a single-step shape.  0 if ctx is NULL or variant out of
+ * range. */
+int lbm_variant_steps(const lbm_ctx_t *ctx, int32_t variant);
+
 /* Write rho, ux, uy of the current state (Sec. II.A moments of the
  * populations every node holds before its next collision) into host arrays
  * of nx*ny doubles (concatenated over instances for a batch); any pointer may
@@ -229,8 +238,10 @@ int lbm_info(const lbm_ctx_t *ctx, int64_t *steps_done, int64_t *nodes, int64_t 
 /* Destroy a context; NULL-safe; never frees caller memory.  Synchronises. */
 void lbm_free(lbm_ctx_t *ctx);
 
-/* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16) on
- * hip_stream: a reference for achievable HBM bandwidth. */
+/* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16; 0 is a
+ * no-op) on hip_stream: a reference for achievable HBM bandwidth.  Each thread
+ * moves four 16-byte vectors with non-temporal loads and stores.  dst and src
+ * are device pointers that must not overlap. */
 int lbm_copy_kernel(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Message of the last error on this thread, and the text of an error code. */

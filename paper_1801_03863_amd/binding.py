@@ -92,6 +92,7 @@ _sig("lbm_autotune", ctypes.c_int, [_V, ctypes.c_char_p, ctypes.POINTER(ctypes.c
 _sig("lbm_set_variant", ctypes.c_int, [_V, ctypes.c_int32])
 _sig("lbm_variant_count", ctypes.c_int, [_V])
 _sig("lbm_variant_name", ctypes.c_char_p, [_V, ctypes.c_int32])
+_sig("lbm_variant_steps", ctypes.c_int, [_V, ctypes.c_int32])
 _sig("lbm_set_plane_pad", ctypes.c_int, [_V, ctypes.c_int32])
 _sig("lbm_set_batch_steps", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.c_int32])
 _sig("lbm_get_layout", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)])
@@ -243,6 +244,12 @@ def lbm_get_layout(ctx):
 
 def lbm_variant_name(ctx, v):
     return _lib.lbm_variant_name(ctx, int(v)).decode()
+
+
+def lbm_variant_steps(ctx, v):
+    """Steps one launch of shape v takes (1, or 2 for the temporally blocked
+    single-lattice D2Q9 shapes)."""
+    return _lib.lbm_variant_steps(ctx, int(v))
 
 
 def lbm_info(ctx):

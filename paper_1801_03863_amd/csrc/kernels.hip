@@ -664,6 +664,187 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 }
 
 // --------------------------------------------------------------------------
+// D2Q9, one lattice, two steps per launch (temporal blocking).
+//
+// A block of BX threads owns an output tile of BX columns and H rows.  It
+// walks a window that is one node wider on every side: window column i is
+// lattice column x0 - 1 + i and window row j is lattice row y0 - 1 + j, each
+// mapped into the lattice by the neighbour rule (wrapped on periodic axes,
+// clamped otherwise).  The first step computes every window node exactly as
+// the single-step kernels compute that lattice node, and rounds it to the
+// storage type into LDS; the second step computes the tile's own nodes from
+// those values and writes them to HBM.  Because the window rows and columns
+// around a node are precisely its neighbour rows and columns, every result
+// is bitwise equal to two single-step launches, while HBM sees one read and
+// one write of each population per two steps.
+//
+// The first step runs row by row (thread t: column x0 + t) into a ring of RS
+// window rows, and the second step trails it by one row.  With four slots one
+// barrier per row suffices (the row written in iteration j + 1 was last read
+// in iteration j - 1); three slots take less LDS, and so leave room for more
+// blocks per CU, at the cost of a second barrier per row.  The two halo columns of every window row are computed
+// first, by the first 2 (H + 2) threads, into their own LDS array, and copied
+// into the ring as each row is written.  Each first-step row's loads are
+// issued one iteration ahead, before the barrier, and complete during the
+// second step of the row before.
+// Only nodes inside the tile report status (first step at a.step, second at
+// a.step + 1), so every node reports once per step.
+// --------------------------------------------------------------------------
+
+// LDS of the two-step kernel: the ring of rs window rows (nine planes of
+// bx + 2 columns) and the halo columns of every window row.
+template <class T>
+constexpr size_t t2_lds_bytes(int bx, int h, int rs)
+{
+    return sizeof(T) * (size_t)9 * (size_t)(rs * (bx + 2) + 2 * (h + 2));
+}
+
+// Lattice coordinate of window coordinate g on an axis of n nodes: the
+// neighbour rule one node beyond either edge (wrap or clamp); coordinates
+// further out (ragged last tiles) are clamped, and those nodes are computed
+// but never read.
+__device__ __forceinline__ int t2_map(int g, int n, bool wrap)
+{
+    if (g < 0) return wrap ? n - 1 : 0;
+    if (g >= n) return (wrap && g == n) ? 0 : n - 1;
+    return g;
+}
+
+// Workgroup barrier that orders LDS accesses only, so global loads issued
+// before it stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
+__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *__restrict__ dst, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    constexpr int W = BX + 2;     // window columns
+    constexpr int SLOT = 9 * W;   // one window row: nine planes
+    extern __shared__ __align__(16) unsigned char t2_lds[];
+    static_assert(RS == 3 || RS == 4, "ring of three or four window rows");
+    T *ring = (T *)t2_lds;        // [RS][9][W]
+    T *halo = ring + RS * SLOT;   // [H + 2][2][9]
+    const Inst &in = a.one;
+    const int nx = in.nx, ny = in.ny;
+    const int64_t P = in.plane;
+    const bool xw = a.bc == BC_PERIODIC;
+    const bool yw = a.bc == BC_PERIODIC || a.bc == BC_TUBE;
+    const bool cavity = a.bc == BC_CAVITY;
+    int tx, ty;
+    tile_of_block(0, a.tiles_x, tx, ty);
+    const int t = (int)threadIdx.x;
+    const int x0 = tx * BX, y0 = ty * H;
+    const int hn = min(H, ny - y0);  // output rows of this tile (block-uniform)
+    const int x = x0 + t;
+    const bool xin = x < nx;
+    const int xs = t2_map(x, nx, xw);  // lattice column of this thread's window column
+    const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(T));
+    C ref[9];
+    ref9<C>(C(in.rho0), ref);
+
+    // The first window row's loads are issued first, so that they are in
+    // flight during the halo columns' first step.
+    const int nj = hn + 2;
+    auto row_of = [&](int j) { return t2_map(y0 - 1 + j, ny, yw); };
+    auto pull_row = [&](int j, T (&r)[9]) {
+        const int gy = row_of(j);
+        if (cavity && gy == ny - 1) return;  // the lid row loads nothing
+        const Nb n = neighbours(0, gy, 1, ny, a.bc);  // rows only
+        pull9_cols<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, r);
+    };
+    T raw[9];
+    pull_row(0, raw);
+
+    // Halo columns (x0 - 1 and x0 + BX) of every window row, first step.
+    for (int k = t; k < 2 * (hn + 2); k += BX) {
+        const int side = k & 1, j = k >> 1;
+        const int gx = t2_map(side ? x0 + BX : x0 - 1, nx, xw);
+        const int gy = row_of(j);
+        C f[9];
+        const Nb n = neighbours(gx, gy, nx, ny, a.bc);
+        pull9<ST>(src, P, gx, gy, nx, n, ref, a.fp16_iscale, f);
+        (void)node9<ST, CO>(f, role9(gx, gy, nx, ny, a.bc), in);
+        T *h = halo + (j * 2 + side) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) store<ST>(h + q, f[q], ref[q], a.fp16_scale);
+    }
+
+    int bad1 = kNoNode, bad2 = kNoNode;
+    int guarded = 0;
+    lds_barrier();  // halo array complete
+
+    // Iteration j: first step of window row j from raw (loaded in the
+    // iteration before), loads of row j + 1 into raw, barrier, second step of
+    // lattice row y0 + j - 2.
+    for (int j = 0; j < nj; ++j) {
+        // Three slots: the slot written now was read by the last second step.
+        if constexpr (RS == 3) {
+            if (j > 0) lds_barrier();
+        }
+        {
+            const int gy = row_of(j);
+            C f[9];
+            int fl = 0;
+            if (cavity && gy == ny - 1) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) f[q] = C(in.lid[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
+                fl = node9_row<ST, CO>(f, xs, gy, nx, ny, a.bc, in);
+            }
+            const bool own = j >= 1 && j <= hn && xin;
+            if (own && (fl & 1)) bad1 = min(bad1, gy * nx + x);
+            guarded += __popcll(__ballot(own && (fl & 2)));
+            T *row = ring + (j % RS) * SLOT;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) store<ST>(row + q * W + t + 1, f[q], ref[q], a.fp16_scale);
+            if (t < 18) {
+                const int side = t >= 9, q = t - 9 * side;
+                row[q * W + (side ? W - 1 : 0)] = halo[(j * 2 + side) * 9 + q];
+            }
+        }
+        if (j + 1 < nj) pull_row(j + 1, raw);  // completes during this second step
+        lds_barrier();
+        if (j < 2) continue;
+        // Second step, lattice row y = y0 + j - 2 (window row j - 1): window
+        // rows j - 2 and j hold its neighbour rows, window columns t and
+        // t + 2 its neighbour columns.
+        const int y = y0 + j - 2;
+        if (cavity && y == ny - 1) {
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            continue;
+        }
+        const T *rm = ring + ((j - 2) % RS) * SLOT + t;
+        const T *rc = ring + ((j - 1) % RS) * SLOT + t;
+        const T *rp = ring + (j % RS) * SLOT + t;
+        C f[9];
+        f[0] = load<ST>(rc + 0 * W + 1, ref[0], a.fp16_iscale);
+        f[1] = load<ST>(rc + 1 * W + 0, ref[1], a.fp16_iscale);
+        f[2] = load<ST>(rm + 2 * W + 1, ref[2], a.fp16_iscale);
+        f[3] = load<ST>(rc + 3 * W + 2, ref[3], a.fp16_iscale);
+        f[4] = load<ST>(rp + 4 * W + 1, ref[4], a.fp16_iscale);
+        f[5] = load<ST>(rm + 5 * W + 0, ref[5], a.fp16_iscale);
+        f[6] = load<ST>(rm + 6 * W + 2, ref[6], a.fp16_iscale);
+        f[7] = load<ST>(rp + 7 * W + 2, ref[7], a.fp16_iscale);
+        f[8] = load<ST>(rp + 8 * W + 0, ref[8], a.fp16_iscale);
+        const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
+        if (xin && (fl & 1)) bad2 = min(bad2, y * nx + x);
+        guarded += __popcll(__ballot(xin && (fl & 2)));
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+    }
+    report(a.status, bad1, guarded, a.step, a.step_base);
+    report(a.status, bad2, 0, a.step + 1, a.step_base);
+}
+
+// --------------------------------------------------------------------------
 // D2Q9, batch of lattices.  A tile is BLK consecutive nodes (row-major) of
 // one instance; tile tables give its instance and first node.
 // --------------------------------------------------------------------------
@@ -1133,11 +1314,33 @@ __global__ void k_gather(Inst in, int bc, const typename Form<ST>::T *__restrict
     if (uy) uy[i] = jy / r;
 }
 
-__global__ void k_copy(uint4 *__restrict__ d, const uint4 *__restrict__ s, size_t n)
+// Each thread moves kCopyVec 16-byte vectors, one block-width apart, so every
+// load instruction of a wave covers 1 KiB of contiguous memory and a thread
+// has kCopyVec loads in flight before its first store.
+constexpr int kCopyVec = 4;
+
+__global__ __launch_bounds__(256) void k_copy(u32x4 *__restrict__ d, const u32x4 *__restrict__ s, size_t n)
 {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) d[i] = s[i];
+    const size_t b0 = (size_t)blockIdx.x * (256 * kCopyVec);
+    const size_t i0 = b0 + threadIdx.x;
+    u32x4 v[kCopyVec];
+    if (b0 + 256 * kCopyVec <= n) {  // whole block: no per-vector test, loads all in flight
+#pragma unroll
+        for (int j = 0; j < kCopyVec; ++j) v[j] = __builtin_nontemporal_load(s + i0 + (size_t)j * 256);
+#pragma unroll
+        for (int j = 0; j < kCopyVec; ++j) __builtin_nontemporal_store(v[j], d + i0 + (size_t)j * 256);
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < kCopyVec; ++j) {
+        const size_t i = i0 + (size_t)j * 256;
+        if (i < n) v[j] = __builtin_nontemporal_load(s + i);
+    }
+#pragma unroll
+    for (int j = 0; j < kCopyVec; ++j) {
+        const size_t i = i0 + (size_t)j * 256;
+        if (i < n) __builtin_nontemporal_store(v[j], d + i);
+    }
 }
 
 __global__ void k_step_base(int64_t *b, int64_t v, int add)
@@ -1165,6 +1368,7 @@ namespace {
 struct Shape {
     int bx, by, rpt, swz;
     const char *name;
+    int steps = 1;  // steps per launch
 };
 
 // Launch shapes of the single-lattice D2Q9 kernel.  Every shape computes the
@@ -1196,7 +1400,21 @@ constexpr Shape kShapes[] = {
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store prio"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=6 prio"},
     {256, 1, 1, 0, "256x1 rows=1 linear nt-load(unshifted planes) nt-store waves>=8 prio"},
+    {256, 32, 1, 0, "two steps per launch, 256x32 tiles, nt-load(unshifted planes) nt-store", 2},
+    {256, 16, 1, 0, "two steps per launch, 256x16 tiles, nt-load(unshifted planes) nt-store", 2},
+    {256, 64, 1, 0, "two steps per launch, 256x64 tiles, nt-load(unshifted planes) nt-store", 2},
+    {128, 32, 1, 0, "two steps per launch, 128x32 tiles, nt-load(unshifted planes) nt-store", 2},
+    {512, 32, 1, 0, "two steps per launch, 512x32 tiles, nt-load(unshifted planes) nt-store", 2},
+    {256, 32, 1, 0, "two steps per launch, 256x32 tiles, nt-store", 2},
+    {256, 16, 1, 0, "two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store", 2},
+    {256, 16, 1, 0, "two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
+    {128, 16, 1, 0, "two steps per launch, 128x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
+    {256, 24, 1, 0, "two steps per launch, 256x24 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
+    {512, 16, 1, 0, "two steps per launch, 512x16 tiles, nt-load(unshifted planes) nt-store", 2},
 };
+// Single-step shape that takes the last step of an odd step count when a
+// two-step shape is selected (every shape gives the same bits).
+constexpr int kOddStepShape = 20;
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
 constexpr int kNumShapesOther = 3;  // the other collision rules instantiate the first three
@@ -1242,6 +1460,56 @@ hipError_t go9pf(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
+hipError_t go9t2(const void *src, void *dst, StepArgs a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int tiles_x = (a.one.nx + BX - 1) / BX;
+    const int tiles_y = (a.one.ny + H - 1) / H;
+    a.tiles_x = tiles_x;
+    a.xcd_swizzle = 0;
+    const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
+    hipLaunchKernelGGL((k_d2q9_t2<ST, CO, BX, H, RS, NT, WPE>), grid, dim3(BX), t2_lds_bytes<T>(BX, H, RS), s,
+                       (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+// LDS beyond the default 64 KiB must be allowed per kernel before launch
+// (outside any stream capture): the FP64 two-step tiles need it.
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
+hipError_t prep9t2()
+{
+    using T = typename Form<ST>::T;
+    constexpr size_t b = t2_lds_bytes<T>(BX, H, RS);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_d2q9_t2<ST, CO, BX, H, RS, NT, WPE>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+// Two-step shapes of the single-lattice kernel (MinxEnt4): launch, or with
+// `prep` only set the kernel's LDS limit.
+template <int ST, int CO>
+hipError_t dispatch9t2(int v, bool prep, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+#define LBM_T2(BX, H, RS, NT, WPE) \
+    return prep ? prep9t2<ST, CO, BX, H, RS, NT, WPE>() : go9t2<ST, CO, BX, H, RS, NT, WPE>(src, dst, a, s)
+    switch (v) {
+    case 26: LBM_T2(256, 32, 4, 6, 0);
+    case 27: LBM_T2(256, 16, 4, 6, 0);
+    case 28: LBM_T2(256, 64, 4, 6, 0);
+    case 29: LBM_T2(128, 32, 4, 6, 0);
+    case 30: LBM_T2(512, 32, 4, 6, 0);
+    case 31: LBM_T2(256, 32, 4, 2, 0);
+    case 32: LBM_T2(256, 16, 3, 6, 0);
+    case 33: LBM_T2(256, 16, 3, 6, 5);
+    case 34: LBM_T2(128, 16, 3, 6, 5);
+    case 35: LBM_T2(256, 24, 3, 6, 5);
+    case 36: LBM_T2(512, 16, 4, 6, 0);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBM_T2
+}
+
 template <int ST, int CO>
 hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
@@ -1277,7 +1545,7 @@ hipError_t dispatch9(int v, const void *src, void *dst, const StepArgs &a, hipSt
         case 23: return go9<ST, CO, 256, 1, 1, 14>(src, dst, a, swz, s);
         case 24: return go9<ST, CO, 256, 1, 1, 14, 6>(src, dst, a, swz, s);
         case 25: return go9<ST, CO, 256, 1, 1, 14, 8>(src, dst, a, swz, s);
-        default: break;
+        default: return dispatch9t2<ST, CO>(v, false, src, dst, a, s);
         }
     }
     return hipErrorInvalidValue;
@@ -1466,6 +1734,24 @@ hipError_t gather_st(int lattice, const Inst &in, int bc, const void *buf, doubl
 }  // namespace
 
 int d2q9_variant_count(int coll) { return coll == CO_MINXENT4 ? kNumShapes : kNumShapesOther; }
+int d2q9_variant_steps(int coll, int v)
+{
+    return (coll == CO_MINXENT4 && v >= 0 && v < kNumShapes) ? kShapes[v].steps : 1;
+}
+int d2q9_odd_step_variant() { return kOddStepShape; }
+
+hipError_t prepare_d2q9_variant(int st, int coll, int v)
+{
+    if (d2q9_variant_steps(coll, v) != 2) return hipSuccess;
+    const StepArgs none{};
+    switch (st) {
+    case ST_F64: return dispatch9t2<ST_F64, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F32N64: return dispatch9t2<ST_F32N64, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F32: return dispatch9t2<ST_F32, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F16DEV: return dispatch9t2<ST_F16DEV, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    default: return hipErrorInvalidValue;
+    }
+}
 const char *d2q9_variant_name(int v) { return (v >= 0 && v < kNumShapes) ? kShapes[v].name : "?"; }
 int d1q3_variant_count() { return kNumShapes3; }
 const char *d1q3_variant_name(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].name : "?"; }
@@ -1599,7 +1885,10 @@ hipError_t launch_gather(int lattice, int st, const Inst &in, int bc, const void
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n);
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 256 * kCopyVec - 1) / (256 * kCopyVec);
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4 *)dst, (const u32x4 *)src, n);
     return hipGetLastError();
 }
 

@@ -54,6 +54,13 @@ struct StepArgs {
 // Host-side launchers (return hipError_t of the launch).
 int d2q9_variant_count(int coll);
 const char *d2q9_variant_name(int variant);
+// Steps one launch of a single-lattice D2Q9 shape takes (1, or 2 for the
+// temporally blocked shapes), the single-step shape that takes the last step
+// of an odd count, and the host-side set-up a shape needs before its first
+// launch (call outside stream capture).
+int d2q9_variant_steps(int coll, int variant);
+int d2q9_odd_step_variant();
+hipError_t prepare_d2q9_variant(int st, int coll, int variant);
 hipError_t launch_d2q9_step(int storage, int coll, int variant, const void *src, void *dst,
                             const StepArgs &a, hipStream_t s);
 hipError_t launch_d2q9_batch_step(int storage, int coll, int variant, const void *src, void *dst,

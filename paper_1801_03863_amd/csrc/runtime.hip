@@ -301,6 +301,29 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
     return lbm::launch_d1q3_step(c->storage, variant, src, dst, a, s);
 }
 
+// Steps one launch of shape v takes: 2 for the temporally blocked
+// single-lattice D2Q9 shapes, else 1.
+int launch_steps(const lbm_ctx *c, int v)
+{
+    return (!c->batch && c->b == 9) ? lbm::d2q9_variant_steps(c->p.collision, v) : 1;
+}
+
+// Launch `n` (1 or 2) steps of the context's shape from buf[cur]: the state
+// ends in buf[cur ^ 1] either way.  One step of a two-step shape runs on a
+// single-step shape.
+hipError_t launch_steps_from(const lbm_ctx *c, int v, int n, int cur, const lbm::StepArgs &a, hipStream_t s)
+{
+    if (launch_steps(c, v) == 2 && n == 1) v = lbm::d2q9_odd_step_variant();
+    return launch_step(c, v, c->buf[cur], c->buf[cur ^ 1], a, s);
+}
+
+// Launches that replay `steps` steps with shape v, which sets how often the
+// two buffers swap.
+int64_t launches_for(const lbm_ctx *c, int v, int64_t steps)
+{
+    return launch_steps(c, v) == 2 ? steps / 2 + (steps & 1) : steps;
+}
+
 int variant_count(const lbm_ctx *c)
 {
     if (c->batch) return lbm::batch_variant_count(c->b) + (c->lds_variant >= 0 ? 1 : 0);
@@ -324,10 +347,13 @@ int capture_graph(lbm_ctx *c, int parity)
     HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     int cur = parity;
     hipError_t err = hipSuccess;
-    for (int k = 0; k < c->graph_chunk && err == hipSuccess; ++k) {
+    const int spl = launch_steps(c, c->variant);
+    for (int k = 0; k < c->graph_chunk && err == hipSuccess;) {
+        const int n = std::min(spl, c->graph_chunk - k);
         lbm::StepArgs a = step_args(c, c->d_status, k, c->d_step_base);
-        err = launch_step(c, c->variant, c->buf[cur], c->buf[cur ^ 1], a, c->cap_stream);
+        err = launch_steps_from(c, c->variant, n, cur, a, c->cap_stream);
         cur ^= 1;
+        k += n;
     }
     if (err == hipSuccess) err = lbm::launch_add_step_base(c->d_step_base, c->graph_chunk, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
@@ -582,16 +608,17 @@ int lbm_step(lbm_ctx_t *c, int64_t nsteps)
             }
             HIPCHK(hipGraphLaunch(c->gexec[c->cur], c->stream));
             c->steps_done += c->graph_chunk;
-            if (c->graph_chunk & 1) c->cur ^= 1;
+            if (launches_for(c, c->variant, c->graph_chunk) & 1) c->cur ^= 1;
             i += c->graph_chunk;
             continue;
         }
+        const int n = (int)std::min<int64_t>(launch_steps(c, c->variant), nsteps - i);
         lbm::StepArgs a = step_args(c, c->d_status, c->steps_done, nullptr);
-        HIPCHK(launch_step(c, c->variant, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+        HIPCHK(launch_steps_from(c, c->variant, n, c->cur, a, c->stream));
         c->cur ^= 1;
-        c->steps_done += 1;
+        c->steps_done += n;
         c->base_synced = false;
-        ++i;
+        i += n;
     }
     return LBM_OK;
 }
@@ -612,6 +639,7 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
     if (c->stream) HIPCHK(hipStreamSynchronize(c->stream));
     else HIPCHK(hipDeviceSynchronize());
     drop_graphs(c);
+    if (!c->batch && c->b == 9) HIPCHK(lbm::prepare_d2q9_variant(c->storage, c->p.collision, v));
     c->variant = v;
     if (c->batch && v != c->lds_variant && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes)
         return build_tiles(c, lbm::batch_tile_nodes(c->b, v));
@@ -619,6 +647,12 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
 }
 
 int lbm_variant_count(const lbm_ctx_t *c) { return c ? variant_count(c) : 0; }
+
+int lbm_variant_steps(const lbm_ctx_t *c, int32_t v)
+{
+    if (!c || v < 0 || v >= variant_count(c)) return 0;
+    return launch_steps(c, v);
+}
 
 int lbm_set_plane_pad(lbm_ctx_t *c, int32_t pad_bytes)
 {
@@ -699,12 +733,13 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
     // Time `n` launches of shape v (the source buffer is the current state
     // and is never written: the persistent shape runs an odd number of
     // steps, ending in the other buffer); best of `trials`, in ms per `reps`
-    // launches.
+    // steps (a two-step shape takes two per launch).
     auto time_shape = [&](int v, int n, int trials, float &out) -> int {
         int rc = lbm_set_variant(c, v);
         if (rc) return rc;
         const bool pers = c->batch && v == c->lds_variant;
         const int pn = n | 1;
+        const int spl = launch_steps(c, v);
         float best_t = 1e30f;
         for (int trial = 0; trial < trials; ++trial) {
             HIPCHK(hipEventRecord(e0, c->stream));
@@ -720,7 +755,7 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            ms *= (float)reps / (float)(pers ? pn : n);
+            ms *= (float)reps / (float)(pers ? pn : n * spl);
             best_t = std::min(best_t, ms);
         }
         out = best_t;
@@ -736,11 +771,11 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
         t1.emplace_back(ms, v);
     }
     std::sort(t1.begin(), t1.end());
-    // Stage 2: the three fastest again with four times longer trials, taken
+    // Stage 2: the five fastest again with four times longer trials, taken
     // in turn so that clock drift affects them alike.
-    const int nc = (int)std::min<size_t>(3, t1.size());
+    const int nc = (int)std::min<size_t>(5, t1.size());
     std::vector<float> t2(nc, 1e30f);
-    for (int round = 0; round < 3; ++round) {
+    for (int round = 0; round < 4; ++round) {
         for (int k = 0; k < nc; ++k) {
             float ms = 0.0f;
             int rc = time_shape(t1[k].second, 4 * reps, 1, ms);

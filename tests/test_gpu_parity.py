@@ -348,14 +348,19 @@ def test_argument_errors_leave_the_context_usable():
     assert_close(g, o, fluid_mask("d2q9", "cavity", nx, ny), TOL64, label="after errors")
 
 
-def test_copy_kernel():
+@pytest.mark.parametrize("nbytes", [0, 16, 4096, 16384 + 48, (1 << 22) + 16 * 1023, 3 << 20])
+def test_copy_kernel(nbytes):
+    """Whole blocks, a ragged last block and sizes below one block; the bytes
+    after the copied range keep their value."""
     import torch
     b = B()
-    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
-    dst = torch.zeros_like(src)
-    b.lbm_copy_kernel(dst, src, src.numel() * 4)
+    n = nbytes // 4
+    src = torch.arange(n + 64, dtype=torch.int32, device="cuda")
+    dst = torch.full_like(src, -7)
+    b.lbm_copy_kernel(dst, src, nbytes)
     torch.cuda.synchronize()
-    assert torch.equal(src, dst)
+    assert torch.equal(src[:n], dst[:n])
+    assert bool((dst[n:] == -7).all())
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,116 @@
+"""Two steps per launch (the temporally blocked single-lattice D2Q9 shapes).
+
+Each such launch computes one step into LDS and the next from there, so its
+results must be bitwise equal to two single-step launches: for every boundary
+kind, for lattices smaller than, equal to and ragged against one tile, for odd
+step counts (the last step then runs on a single-step shape), under graph
+replay, and with the same status records (first unstable step and node,
+guarded count), wherever the event falls inside a launch.
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import B, field_errors, fluid_mask, gpu_run, orc_run, smooth_fields
+
+pytestmark = pytest.mark.gpu
+
+SINGLE = 0  # a single-step shape
+
+
+def two_step_shapes():
+    b = B()
+    z = np.zeros((8, 8))
+    ctx = b.lbm_init(b.make_params("d2q9", "minxent4", "cavity", "fp64", 8, 8, 0.6, 0.0, 0.1, 1.0),
+                     np.ones((8, 8)), z, z)
+    try:
+        vs = [v for v in range(b.lbm_variant_count(ctx)) if "two steps" in b.lbm_variant_name(ctx, v)]
+    finally:
+        b.lbm_free(ctx)
+    assert vs
+    return vs
+
+
+def _status(s):
+    return (s["unstable"], s["first_step"], s["first_node"], s["guarded"])
+
+
+@pytest.mark.parametrize("bc", ["cavity", "box", "tube", "periodic"])
+@pytest.mark.parametrize("nx,ny", [(300, 131), (257, 65), (33, 17), (3, 3)])
+def test_two_step_shapes_bitwise_every_boundary(bc, nx, ny):
+    rho, ux, uy = smooth_fields(nx, ny, seed=nx + ny)
+    for steps in (10, 7):
+        ref = gpu_run("d2q9", "minxent4", bc, "fp32_newton64", nx, ny, 0.6, rho, ux, uy, steps=steps, u_lid=0.1,
+                      variant=SINGLE, want_f=True)
+        for v in two_step_shapes():
+            g = gpu_run("d2q9", "minxent4", bc, "fp32_newton64", nx, ny, 0.6, rho, ux, uy, steps=steps, u_lid=0.1,
+                        variant=v, want_f=True)
+            assert np.array_equal(g["f"], ref["f"]), (v, steps)
+            assert _status(g["status"]) == _status(ref["status"]), (v, steps)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_two_step_shapes_bitwise_every_form(precision):
+    nx, ny = 530, 97  # ragged in both directions for every tile shape
+    rho, ux, uy = smooth_fields(nx, ny, seed=31)
+    ref = gpu_run("d2q9", "minxent4", "cavity", precision, nx, ny, 0.58, rho, ux, uy, steps=12, u_lid=0.1,
+                  variant=SINGLE, want_f=True)
+    for v in two_step_shapes():
+        g = gpu_run("d2q9", "minxent4", "cavity", precision, nx, ny, 0.58, rho, ux, uy, steps=12, u_lid=0.1,
+                    variant=v, want_f=True)
+        assert np.array_equal(g["f"], ref["f"]), v
+
+
+def test_two_step_fp64_matches_oracle():
+    nx, ny = 270, 70
+    rho, ux, uy = smooth_fields(nx, ny, seed=32)
+    o = orc_run("d2q9", "minxent4", "cavity", nx, ny, 0.6, rho, ux, uy, steps=6, u_lid=0.1)
+    m = fluid_mask("d2q9", "cavity", nx, ny)
+    for v in two_step_shapes():
+        g = gpu_run("d2q9", "minxent4", "cavity", "fp64", nx, ny, 0.6, rho, ux, uy, steps=6, u_lid=0.1, variant=v)
+        e = field_errors(g, o, m)
+        assert all(x[0] <= 1e-12 for x in e.values()), (v, e)
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 5, 8])
+def test_two_step_graph_replay_is_bitwise(chunk):
+    nx, ny = 77, 64
+    rho, ux, uy = smooth_fields(nx, ny, seed=33)
+    v = two_step_shapes()[0]
+    a = gpu_run("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.58, rho, ux, uy, steps=41, u_lid=0.1,
+                variant=SINGLE, want_f=True)
+    g = gpu_run("d2q9", "minxent4", "cavity", "fp32_newton64", nx, ny, 0.58, rho, ux, uy, steps=41, u_lid=0.1,
+                variant=v, graph=chunk, want_f=True)
+    assert np.array_equal(a["f"], g["f"])
+    assert _status(a["status"]) == _status(g["status"])
+
+
+# Periodic 40 x 30 lattices, MinxEnt4 at tau = 0.501, whose first unstable
+# event falls on step 1, 2 or 3 (found with the oracle; seeds of
+# smooth_fields with density amplitude 0.2).
+UNSTABLE = [(0.38, 3, 1), (0.36, 3, 2), (0.36, 0, 3)]
+
+
+@pytest.mark.parametrize("amp,seed,first", UNSTABLE)
+@pytest.mark.parametrize("lead", [0, 1])
+def test_two_step_status_matches_oracle_wherever_the_event_falls(amp, seed, first, lead):
+    # lead = 1 takes one single step first, so that every two-step launch
+    # starts on an odd step and the event moves to the other half of a launch.
+    nx, ny = 40, 30
+    rho, ux, uy = smooth_fields(nx, ny, seed=seed, amp=amp, rho_amp=0.2)
+    o = orc_run("d2q9", "minxent4", "periodic", nx, ny, 0.501, rho, ux, uy, steps=9)
+    assert o["unstable"] and o["first_step"] == first
+    b = B()
+    p = b.make_params("d2q9", "minxent4", "periodic", "fp64", nx, ny, 0.501, 0.0, 0.0, 1.0)
+    for v in two_step_shapes():
+        ctx = b.lbm_init(p, rho, ux, uy)
+        try:
+            b.lbm_set_variant(ctx, v)
+            if lead:
+                b.lbm_step(ctx, 1)
+            b.lbm_step(ctx, 9 - lead)
+            s = b.lbm_status(ctx)
+        finally:
+            b.lbm_free(ctx)
+        assert s["unstable"], v
+        assert (s["first_step"], s["first_node"], s["guarded"]) == (o["first_step"], o["first_node"], o["guarded"]), v
