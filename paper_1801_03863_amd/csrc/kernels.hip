@@ -66,14 +66,22 @@ __device__ __forceinline__ _Float16 enc16(float v, float ref, float scale)
     return (_Float16)__builtin_fmaf(v, scale, -(ref * scale));
 }
 
+// A population in its storage form (rounded to the storage type, or the
+// scaled FP16 deviation).
+template <int ST>
+__device__ __forceinline__ typename Form<ST>::T to_storage(typename Form<ST>::C v, typename Form<ST>::C ref,
+                                                           float scale)
+{
+    using T = typename Form<ST>::T;
+    if constexpr (ST == ST_F16DEV) return enc16(v, ref, scale);
+    else return T(v);
+}
+
 template <int ST, bool NT = false>
 __device__ __forceinline__ void store(typename Form<ST>::T *p, typename Form<ST>::C v, typename Form<ST>::C ref,
                                       float scale)
 {
-    using T = typename Form<ST>::T;
-    T t;
-    if constexpr (ST == ST_F16DEV) t = enc16(v, ref, scale);
-    else t = T(v);
+    const typename Form<ST>::T t = to_storage<ST>(v, ref, scale);
     if constexpr (NT) __builtin_nontemporal_store(t, p);
     else *p = t;
 }
@@ -678,11 +686,17 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // is bitwise equal to two single-step launches, while HBM sees one read and
 // one write of each population per two steps.
 //
-// The first step runs row by row (thread t: column x0 + t) into a ring of RS
-// window rows, and the second step trails it by one row.  With four slots one
-// barrier per row suffices (the row written in iteration j + 1 was last read
-// in iteration j - 1); three slots take less LDS, and so leave room for more
-// blocks per CU, at the cost of a second barrier per row.  The two halo columns of every window row are computed
+// The first step runs row by row (thread t: column x0 + t) and the second
+// step trails it by one row.  RS = 4 or 3 keeps all nine planes of a window
+// row in a ring of RS rows: with four slots one barrier per row suffices (the
+// row written in iteration j + 1 was last read in iteration j - 1); three
+// take less LDS and a second barrier.  RS = 0 splits the planes by how long
+// they are needed: the second step reads the unshifted planes 0, 2 and 4 only
+// in the thread's own column, so they stay in registers (plane 4 of the row
+// just computed, plane 0 of the row before, plane 2 of the row before that);
+// planes 7 and 8 are read in the iteration that writes them (two slots),
+// 1 and 3 one iteration later (three), 5 and 6 two iterations later (four).
+// That is 18 plane-rows of LDS instead of 36, with one barrier per row.  The two halo columns of every window row are computed
 // first, by the first 2 (H + 2) threads, into their own LDS array, and copied
 // into the ring as each row is written.  Each first-step row's loads are
 // issued one iteration ahead, before the barrier, and complete during the
@@ -691,12 +705,15 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // a.step + 1), so every node reports once per step.
 // --------------------------------------------------------------------------
 
-// LDS of the two-step kernel: the ring of rs window rows (nine planes of
-// bx + 2 columns) and the halo columns of every window row.
+// Plane-rows of LDS the ring of the two-step kernel holds (RS as there).
+constexpr int t2_plane_rows(int rs) { return rs == 0 ? 18 : 9 * rs; }
+
+// LDS of the two-step kernel: the ring (plane-rows of bx + 2 columns) and
+// the nine planes of the halo columns of every window row.
 template <class T>
 constexpr size_t t2_lds_bytes(int bx, int h, int rs)
 {
-    return sizeof(T) * (size_t)9 * (size_t)(rs * (bx + 2) + 2 * (h + 2));
+    return sizeof(T) * (size_t)(t2_plane_rows(rs) * (bx + 2) + 18 * (h + 2));
 }
 
 // Lattice coordinate of window coordinate g on an axis of n nodes: the
@@ -726,11 +743,21 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
     using C = typename Form<ST>::C;
     using T = typename Form<ST>::T;
     constexpr int W = BX + 2;     // window columns
-    constexpr int SLOT = 9 * W;   // one window row: nine planes
     extern __shared__ __align__(16) unsigned char t2_lds[];
-    static_assert(RS == 3 || RS == 4, "ring of three or four window rows");
-    T *ring = (T *)t2_lds;        // [RS][9][W]
-    T *halo = ring + RS * SLOT;   // [H + 2][2][9]
+    static_assert(RS == 0 || RS == 3 || RS == 4, "ring of three or four window rows, or split rings");
+    T *ring = (T *)t2_lds;                   // RS > 0: [RS][9][W]; RS = 0: planes 7,8 [2][2][W], 1,3 [3][2][W], 5,6 [4][2][W]
+    T *halo = ring + t2_plane_rows(RS) * W;  // [H + 2][2][9]
+    // Plane q of window row j in the ring (q and the ring layout are
+    // compile-time, j is uniform).
+    auto plane = [&](int q, int j) -> T * {
+        if constexpr (RS != 0) {
+            return ring + ((j % RS) * 9 + q) * W;
+        } else {
+            if (q == 7 || q == 8) return ring + ((j & 1) * 2 + (q - 7)) * W;
+            if (q == 1 || q == 3) return ring + (4 + (j % 3) * 2 + (q == 3)) * W;
+            return ring + (10 + (j & 3) * 2 + (q - 5)) * W;  // q = 5, 6
+        }
+    };
     const Inst &in = a.one;
     const int nx = in.nx, ny = in.ny;
     const int64_t P = in.plane;
@@ -783,11 +810,14 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
     // Iteration j: first step of window row j from raw (loaded in the
     // iteration before), loads of row j + 1 into raw, barrier, second step of
     // lattice row y0 + j - 2.
+    constexpr int kShifted[6] = {1, 3, 5, 6, 7, 8};  // planes read in a neighbour column
+    T u0 = T(0), u2a = T(0), u2b = T(0);  // RS = 0: plane 0 of row j - 1, plane 2 of rows j - 1 and j - 2
     for (int j = 0; j < nj; ++j) {
         // Three slots: the slot written now was read by the last second step.
         if constexpr (RS == 3) {
             if (j > 0) lds_barrier();
         }
+        T v0 = T(0), v2 = T(0), v4 = T(0);  // RS = 0: the unshifted planes of row j
         {
             const int gy = row_of(j);
             C f[9];
@@ -803,16 +833,36 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
             const bool own = j >= 1 && j <= hn && xin;
             if (own && (fl & 1)) bad1 = min(bad1, gy * nx + x);
             guarded += __popcll(__ballot(own && (fl & 2)));
-            T *row = ring + (j % RS) * SLOT;
+            if constexpr (RS != 0) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) store<ST>(row + q * W + t + 1, f[q], ref[q], a.fp16_scale);
-            if (t < 18) {
-                const int side = t >= 9, q = t - 9 * side;
-                row[q * W + (side ? W - 1 : 0)] = halo[(j * 2 + side) * 9 + q];
+                for (int q = 0; q < 9; ++q) store<ST>(plane(q, j) + t + 1, f[q], ref[q], a.fp16_scale);
+                if (t < 18) {
+                    const int side = t >= 9, q = t - 9 * side;
+                    plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const int q = kShifted[k];
+                    store<ST>(plane(q, j) + t + 1, f[q], ref[q], a.fp16_scale);
+                }
+                v0 = to_storage<ST>(f[0], ref[0], a.fp16_scale);
+                v2 = to_storage<ST>(f[2], ref[2], a.fp16_scale);
+                v4 = to_storage<ST>(f[4], ref[4], a.fp16_scale);
+                if (t < 12) {
+                    const int side = t >= 6, q = kShifted[t - 6 * side];
+                    plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                }
             }
         }
         if (j + 1 < nj) pull_row(j + 1, raw);  // completes during this second step
         lds_barrier();
+        // Unshifted planes this second step reads from registers (rows j - 1
+        // and j - 2), then the delay line moves on by one row.
+        const T s0 = u0, s2 = u2b;
+        u0 = v0;
+        u2b = u2a;
+        u2a = v2;
         if (j < 2) continue;
         // Second step, lattice row y = y0 + j - 2 (window row j - 1): window
         // rows j - 2 and j hold its neighbour rows, window columns t and
@@ -822,19 +872,22 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
             if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
             continue;
         }
-        const T *rm = ring + ((j - 2) % RS) * SLOT + t;
-        const T *rc = ring + ((j - 1) % RS) * SLOT + t;
-        const T *rp = ring + (j % RS) * SLOT + t;
         C f[9];
-        f[0] = load<ST>(rc + 0 * W + 1, ref[0], a.fp16_iscale);
-        f[1] = load<ST>(rc + 1 * W + 0, ref[1], a.fp16_iscale);
-        f[2] = load<ST>(rm + 2 * W + 1, ref[2], a.fp16_iscale);
-        f[3] = load<ST>(rc + 3 * W + 2, ref[3], a.fp16_iscale);
-        f[4] = load<ST>(rp + 4 * W + 1, ref[4], a.fp16_iscale);
-        f[5] = load<ST>(rm + 5 * W + 0, ref[5], a.fp16_iscale);
-        f[6] = load<ST>(rm + 6 * W + 2, ref[6], a.fp16_iscale);
-        f[7] = load<ST>(rp + 7 * W + 2, ref[7], a.fp16_iscale);
-        f[8] = load<ST>(rp + 8 * W + 0, ref[8], a.fp16_iscale);
+        if constexpr (RS != 0) {
+            f[0] = load<ST>(plane(0, j - 1) + t + 1, ref[0], a.fp16_iscale);
+            f[2] = load<ST>(plane(2, j - 2) + t + 1, ref[2], a.fp16_iscale);
+            f[4] = load<ST>(plane(4, j) + t + 1, ref[4], a.fp16_iscale);
+        } else {
+            f[0] = load<ST>(&s0, ref[0], a.fp16_iscale);
+            f[2] = load<ST>(&s2, ref[2], a.fp16_iscale);
+            f[4] = load<ST>(&v4, ref[4], a.fp16_iscale);
+        }
+        f[1] = load<ST>(plane(1, j - 1) + t, ref[1], a.fp16_iscale);
+        f[3] = load<ST>(plane(3, j - 1) + t + 2, ref[3], a.fp16_iscale);
+        f[5] = load<ST>(plane(5, j - 2) + t, ref[5], a.fp16_iscale);
+        f[6] = load<ST>(plane(6, j - 2) + t + 2, ref[6], a.fp16_iscale);
+        f[7] = load<ST>(plane(7, j) + t + 2, ref[7], a.fp16_iscale);
+        f[8] = load<ST>(plane(8, j) + t, ref[8], a.fp16_iscale);
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         if (xin && (fl & 1)) bad2 = min(bad2, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
@@ -1411,6 +1464,7 @@ constexpr Shape kShapes[] = {
     {128, 16, 1, 0, "two steps per launch, 128x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
     {256, 24, 1, 0, "two steps per launch, 256x24 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
     {512, 16, 1, 0, "two steps per launch, 512x16 tiles, nt-load(unshifted planes) nt-store", 2},
+    {256, 16, 1, 0, "two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2},
 };
 // Single-step shape that takes the last step of an odd step count when a
 // two-step shape is selected (every shape gives the same bits).
@@ -1505,6 +1559,7 @@ hipError_t dispatch9t2(int v, bool prep, const void *src, void *dst, const StepA
     case 34: LBM_T2(128, 16, 3, 6, 5);
     case 35: LBM_T2(256, 24, 3, 6, 5);
     case 36: LBM_T2(512, 16, 4, 6, 0);
+    case 37: LBM_T2(256, 16, 0, 6, 0);
     default: return hipErrorInvalidValue;
     }
 #undef LBM_T2
