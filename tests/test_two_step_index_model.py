@@ -1,0 +1,170 @@
+"""CPU model of the two-step kernel's window and ring indexing.
+
+The two-step D2Q9 kernel computes a first step over a window one node wider
+than its tile into LDS, then the tile's second step from there.  This model
+replays its index logic with numpy on tiny lattices: the window-to-lattice
+mapping (wrap or clamp one node past each edge), the halo columns computed
+up front, the ring slots each window row goes to (four or three full slots,
+or the split rings with the unshifted planes held in a register delay line),
+and the neighbour rows and columns the second step reads.  A stand-in
+collision (a nonlinear mix of the nine values, bounce-back on walls, fixed
+values on the lid) makes any wrong source visible.  Every second-step output
+must equal two plain single steps, and no second step may read a ring entry
+the first step has not written (NaN sentinels).  The model runs one thread
+after another, so it also checks the barrier discipline that makes the
+concurrent kernel equal to it: a slot is written again only once a barrier
+separates that write from every read of its previous contents (each
+iteration has one barrier between its writes and its reads, and the
+three-slot ring a second one before its writes).  The GPU tests check the
+kernel itself; this checks that its indexing scheme is sound.
+"""
+import numpy as np
+import pytest
+
+CX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+CY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+LID = np.linspace(0.1, 0.9, 9).astype(np.float32)
+SHIFTED = [1, 3, 5, 6, 7, 8]
+
+
+def neighbours(x, y, nx, ny, bc):
+    xw, yw = bc == "periodic", bc in ("periodic", "tube")
+    xm = x - 1 if x > 0 else (nx - 1 if xw else 0)
+    xp = x + 1 if x < nx - 1 else (0 if xw else nx - 1)
+    ym = y - 1 if y > 0 else (ny - 1 if yw else 0)
+    yp = y + 1 if y < ny - 1 else (0 if yw else ny - 1)
+    return xm, xp, ym, yp
+
+
+def role(x, y, nx, ny, bc):
+    if bc == "cavity":
+        if y == ny - 1:
+            return "lid"
+        return "wall" if x in (0, nx - 1) or y == 0 else "fluid"
+    if bc == "box":
+        return "wall" if x in (0, nx - 1) or y in (0, ny - 1) else "fluid"
+    if bc == "tube":
+        return "wall" if x in (0, nx - 1) else "fluid"
+    return "fluid"
+
+
+def pull(f, x, y, nx, ny, bc):
+    xm, xp, ym, yp = neighbours(x, y, nx, ny, bc)
+    cols = {0: x, 1: xm, -1: xp}
+    rows = {0: y, 1: ym, -1: yp}
+    return np.array([f[q, rows[CY[q]], cols[CX[q]]] for q in range(9)], dtype=np.float32)
+
+
+def collide(v, r):
+    if r == "lid":
+        return LID.copy()
+    if r == "wall":
+        return v[[0, 3, 4, 1, 2, 7, 8, 5, 6]]
+    return (v + np.float32(0.1) * np.sin(v.sum() * (np.arange(9) + 1))).astype(np.float32)
+
+
+def one_step(f, nx, ny, bc):
+    g = np.zeros_like(f)
+    for y in range(ny):
+        for x in range(nx):
+            g[:, y, x] = collide(pull(f, x, y, nx, ny, bc), role(x, y, nx, ny, bc))
+    return g
+
+
+def window_map(g, n, wrap):
+    if g < 0:
+        return n - 1 if wrap else 0
+    if g >= n:
+        return 0 if (wrap and g == n) else n - 1
+    return g
+
+
+def ring_slot(rs, q, j):
+    """(ring, slot, plane) of plane q of window row j."""
+    if rs:
+        return ("full", j % rs, q)
+    if q in (7, 8):
+        return ("A", j % 2, q - 7)
+    if q in (1, 3):
+        return ("B", j % 3, int(q == 3))
+    return ("C", j % 4, q - 5)
+
+
+def two_steps(f, nx, ny, bc, bx, h, rs):
+    xw, yw = bc == "periodic", bc in ("periodic", "tube")
+    w = bx + 2
+    out = np.full_like(f, np.nan)
+    for ty in range((ny + h - 1) // h):
+        for tx in range((nx + bx - 1) // bx):
+            x0, y0 = tx * bx, ty * h
+            hn = min(h, ny - y0)
+            halo = np.full((h + 2, 2, 9), np.nan, np.float32)
+            for k in range(2 * (hn + 2)):
+                side, j = k & 1, k >> 1
+                gx = window_map(x0 + bx if side else x0 - 1, nx, xw)
+                gy = window_map(y0 - 1 + j, ny, yw)
+                halo[j, side] = collide(pull(f, gx, gy, nx, ny, bc), role(gx, gy, nx, ny, bc))
+            rings = {"full": np.full((max(rs, 1), 9, w), np.nan, np.float32),
+                     "A": np.full((2, 2, w), np.nan, np.float32), "B": np.full((3, 2, w), np.nan, np.float32),
+                     "C": np.full((4, 2, w), np.nan, np.float32)}
+
+            def plane(q, j):
+                r, sl, p = ring_slot(rs, q, j)
+                return rings[r][sl, p]
+
+            # iteration of the last read of each (ring, slot, plane)
+            last_read = {}
+            gap = 1 if rs == 3 else 2
+
+            def read(q, j, it):
+                last_read[ring_slot(rs, q, j)] = it
+                return plane(q, j)
+
+            def write(q, j):
+                key = ring_slot(rs, q, j)
+                assert key not in last_read or j >= last_read[key] + gap, ("slot rewritten too soon", key, j)
+                return plane(q, j)
+
+            u0 = np.full(bx, np.nan, np.float32)
+            u2a, u2b = u0.copy(), u0.copy()
+            for j in range(hn + 2):
+                gy = window_map(y0 - 1 + j, ny, yw)
+                v = np.stack([collide(pull(f, window_map(x0 + t, nx, xw), gy, nx, ny, bc),
+                                      role(window_map(x0 + t, nx, xw), gy, nx, ny, bc)) for t in range(bx)], axis=1)
+                written = range(9) if rs else SHIFTED
+                for q in written:
+                    row = write(q, j)
+                    row[1:bx + 1] = v[q]
+                    row[0] = halo[j, 0, q]
+                    row[w - 1] = halo[j, 1, q]
+                s0, s2 = u0, u2b
+                u0, u2b, u2a = v[0].copy(), u2a, v[2].copy()
+                if j < 2:
+                    continue
+                y = y0 + j - 2
+                for t in range(bx):
+                    x = x0 + t
+                    if x >= nx:
+                        continue
+                    if rs:
+                        p0, p2, p4 = read(0, j - 1, j)[t + 1], read(2, j - 2, j)[t + 1], read(4, j, j)[t + 1]
+                    else:
+                        p0, p2, p4 = s0[t], s2[t], v[4, t]
+                    vals = np.array([p0, read(1, j - 1, j)[t], p2, read(3, j - 1, j)[t + 2], p4,
+                                     read(5, j - 2, j)[t], read(6, j - 2, j)[t + 2], read(7, j, j)[t + 2],
+                                     read(8, j, j)[t]], dtype=np.float32)
+                    assert not np.isnan(vals).any(), ("unwritten ring entry read", tx, ty, x, y)
+                    out[:, y, x] = collide(vals, role(x, y, nx, ny, bc))
+    return out
+
+
+@pytest.mark.parametrize("rs", [4, 3, 0])
+@pytest.mark.parametrize("bc", ["cavity", "box", "tube", "periodic"])
+def test_two_step_indexing_equals_two_single_steps(rs, bc):
+    rng = np.random.default_rng(7)
+    # tiles larger than, equal to and ragged against the lattice; one-row
+    # tiles; several tiles per row and column
+    for nx, ny, bx, h in [(3, 3, 8, 4), (7, 5, 4, 2), (9, 11, 4, 4), (8, 8, 4, 4), (13, 6, 8, 1), (5, 9, 16, 8)]:
+        f = rng.random((9, ny, nx)).astype(np.float32)
+        assert np.array_equal(two_steps(f, nx, ny, bc, bx, h, rs), one_step(one_step(f, nx, ny, bc), nx, ny, bc)), \
+            (nx, ny, bx, h)
