@@ -132,6 +132,7 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, gr
     stream = torch.cuda.current_stream()
     ctx = B.lbm_init_batch(params, rho, ux, uy, workspace=ws, stream=stream)
     variant = B.lbm_autotune(ctx, tune_cache)
+    spl = B.lbm_variant_steps(ctx, variant)
     if graph_chunk > 0:
         B.lbm_set_graph_chunk(ctx, graph_chunk)
     B.lbm_step(ctx, warmup)
@@ -155,7 +156,7 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, gr
     del ws
     return {"wall_s": wall, "event_ms": e0.elapsed_time(e1), "variant": shape, "nodes": info["nodes"],
             "bytes_per_step": info["bytes_per_step"], "fields": {"rho": r, "ux": u, "uy": v}, "status": st,
-            "per_instance": per, "steps_per_launch": 1}
+            "per_instance": per, "steps_per_launch": spl}
 
 
 def rate(res, steps):

@@ -736,16 +736,54 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
-__global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
-void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *__restrict__ dst, StepArgs a)
+// The same ordering within one wave, for tiles a single wave owns: LDS
+// writes before it are visible to every lane of the wave after it.
+__device__ __forceinline__ void lds_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// LDS bytes of one wave's tile in the wave-tiled mode (64 columns), rounded
+// to 16 bytes.
+template <class T>
+constexpr size_t t2_wave_lds_bytes(int h, int rs)
+{
+    return (t2_lds_bytes<T>(64, h, rs) + 15) / 16 * 16;
+}
+
+// WT > 0 (batches): wave-tiled mode.  Each of the block's WT waves owns a
+// tile of 64 columns (BX = 64) from the tile table, with an LDS region of its
+// own; the waves never wait for each other, and a wave without a tile leaves
+// at once.
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0, bool BATCH = false, int WT = 0>
+__global__ __launch_bounds__(WT > 0 ? 64 * WT : BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1)))
+void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<ST>::T *__restrict__ dst_all,
+               StepArgs a)
 {
     using C = typename Form<ST>::C;
     using T = typename Form<ST>::T;
     constexpr int W = BX + 2;     // window columns
     extern __shared__ __align__(16) unsigned char t2_lds[];
     static_assert(RS == 0 || RS == 3 || RS == 4, "ring of three or four window rows, or split rings");
-    T *ring = (T *)t2_lds;                   // RS > 0: [RS][9][W]; RS = 0: planes 7,8 [2][2][W], 1,3 [3][2][W], 5,6 [4][2][W]
+    static_assert(WT == 0 || (BATCH && BX == 64), "wave-tiled mode: batches, 64-column tiles");
+    // Barrier between a row's LDS writes and their reads: the block's, or in
+    // the wave-tiled mode the wave's own.
+    auto sync = [] {
+        if constexpr (WT > 0) lds_wave_sync();
+        else lds_barrier();
+    };
+    // Tile-table entry of this block (or of this wave in the wave-tiled mode).
+    // (The wave index is read from the first lane so that the compiler knows
+    // it, and everything derived from the tile, to be wave-uniform.)
+    const int wave = WT > 0 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+    const int tile = WT > 0 ? (int)blockIdx.x * WT + wave : (int)blockIdx.x;
+    if constexpr (WT > 0) {
+        if (tile >= a.ntiles) return;  // wave-uniform; no block barrier in this mode
+    }
+    T *ring = (T *)(t2_lds + (size_t)wave * (WT > 0 ? t2_wave_lds_bytes<T>(H, RS) : 0));
+    // RS > 0: [RS][9][W]; RS = 0: planes 7,8 [2][2][W], 1,3 [3][2][W], 5,6 [4][2][W]
     T *halo = ring + t2_plane_rows(RS) * W;  // [H + 2][2][9]
     // Plane q of window row j in the ring (q and the ring layout are
     // compile-time, j is uniform).
@@ -758,21 +796,49 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
             return ring + (10 + (j & 3) * 2 + (q - 5)) * W;  // q = 5, 6
         }
     };
-    const Inst &in = a.one;
+    // Instance and tile of this block: a single lattice's grid of tiles, or a
+    // batch's tile table (instance, tile index within the instance).
+    const int ii = BATCH ? a.tile_inst[tile] : 0;
+    const Inst &in = BATCH ? a.inst[ii] : a.one;
     const int nx = in.nx, ny = in.ny;
     const int64_t P = in.plane;
+    const int tiles_x = BATCH ? (nx + BX - 1) / BX : a.tiles_x;
+    int tx, ty;
+    if constexpr (BATCH) {
+        const int k = a.tile_first[tile];
+        ty = k / tiles_x;
+        tx = k - ty * tiles_x;
+    } else {
+        tile_of_block(0, a.tiles_x, tx, ty);
+    }
+    const T *src = src_all + (BATCH ? in.offset : 0);
+    T *dst = dst_all + (BATCH ? in.offset : 0);
+    DevStatus *status = a.status + ii;
     const bool xw = a.bc == BC_PERIODIC;
     const bool yw = a.bc == BC_PERIODIC || a.bc == BC_TUBE;
     const bool cavity = a.bc == BC_CAVITY;
-    int tx, ty;
-    tile_of_block(0, a.tiles_x, tx, ty);
-    const int t = (int)threadIdx.x;
+    const int t = WT > 0 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int x0 = tx * BX, y0 = ty * H;
     const int hn = min(H, ny - y0);  // output rows of this tile (block-uniform)
     const int x = x0 + t;
     const bool xin = x < nx;
     const int xs = t2_map(x, nx, xw);  // lattice column of this thread's window column
-    const Cols cols = columns(xs, tx == 0 || tx == a.tiles_x - 1, nx, a.bc, sizeof(T));
+
+    // Steps this launch takes here (block-uniform): two; one for an odd step
+    // count's last step, or for a batch instance whose step limit falls
+    // between the two (the first step's own nodes then go straight to HBM);
+    // none for a stopped instance, which carries its state over.
+    int kdo = a.max_steps;
+    if constexpr (BATCH) {
+        const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
+        kdo = (int)max((int64_t)0, min((int64_t)kdo, in.stop - s0));
+    }
+    if (kdo <= 0) {
+        if (xin)
+            for (int r = 0; r < hn; ++r) carry_node(src, dst, P, 9, (y0 + r) * nx + x);
+        return;
+    }
+    const Cols cols = columns(xs, tx == 0 || tx == tiles_x - 1, nx, a.bc, sizeof(T));
     C ref[9];
     ref9<C>(C(in.rho0), ref);
 
@@ -805,7 +871,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
 
     int bad1 = kNoNode, bad2 = kNoNode;
     int guarded = 0;
-    lds_barrier();  // halo array complete
+    sync();  // halo array complete
 
     // Iteration j: first step of window row j from raw (loaded in the
     // iteration before), loads of row j + 1 into raw, barrier, second step of
@@ -815,7 +881,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
     for (int j = 0; j < nj; ++j) {
         // Three slots: the slot written now was read by the last second step.
         if constexpr (RS == 3) {
-            if (j > 0) lds_barrier();
+            if (j > 0) sync();
         }
         T v0 = T(0), v2 = T(0), v4 = T(0);  // RS = 0: the unshifted planes of row j
         {
@@ -833,6 +899,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
             const bool own = j >= 1 && j <= hn && xin;
             if (own && (fl & 1)) bad1 = min(bad1, gy * nx + x);
             guarded += __popcll(__ballot(own && (fl & 2)));
+            if (kdo == 1 && own) push9_xy<ST, (NT & 2) != 0>(dst, P, x, gy, nx, f, ref, a.fp16_scale);
             if constexpr (RS != 0) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) store<ST>(plane(q, j) + t + 1, f[q], ref[q], a.fp16_scale);
@@ -856,14 +923,14 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
             }
         }
         if (j + 1 < nj) pull_row(j + 1, raw);  // completes during this second step
-        lds_barrier();
+        sync();
         // Unshifted planes this second step reads from registers (rows j - 1
         // and j - 2), then the delay line moves on by one row.
         const T s0 = u0, s2 = u2b;
         u0 = v0;
         u2b = u2a;
         u2a = v2;
-        if (j < 2) continue;
+        if (j < 2 || kdo == 1) continue;
         // Second step, lattice row y = y0 + j - 2 (window row j - 1): window
         // rows j - 2 and j hold its neighbour rows, window columns t and
         // t + 2 its neighbour columns.
@@ -893,8 +960,8 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::
         guarded += __popcll(__ballot(xin && (fl & 2)));
         if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
     }
-    report(a.status, bad1, guarded, a.step, a.step_base);
-    report(a.status, bad2, 0, a.step + 1, a.step_base);
+    report(status, bad1, guarded, a.step, a.step_base);
+    report(status, bad2, 0, a.step + 1, a.step_base);
 }
 
 // --------------------------------------------------------------------------
@@ -1466,9 +1533,7 @@ constexpr Shape kShapes[] = {
     {512, 16, 1, 0, "two steps per launch, 512x16 tiles, nt-load(unshifted planes) nt-store", 2},
     {256, 16, 1, 0, "two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2},
 };
-// Single-step shape that takes the last step of an odd step count when a
-// two-step shape is selected (every shape gives the same bits).
-constexpr int kOddStepShape = 20;
+
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 constexpr int kMaxGridY = 65535;  // grid y limit; larger tile counts use a 1D grid
 constexpr int kNumShapesOther = 3;  // the other collision rules instantiate the first three
@@ -1620,6 +1685,68 @@ hipError_t dispatch9c(int coll, int v, const void *src, void *dst, const StepArg
 }
 
 
+// Two-step batch shapes: one block per tile of the tile table (a.ntiles).
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
+hipError_t go9bt2(const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    hipLaunchKernelGGL((k_d2q9_t2<ST, CO, BX, H, RS, NT, WPE, true>), dim3(a.ntiles), dim3(BX),
+                       t2_lds_bytes<T>(BX, H, RS), s, (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
+hipError_t prep9bt2()
+{
+    using T = typename Form<ST>::T;
+    constexpr size_t b = t2_lds_bytes<T>(BX, H, RS);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_d2q9_t2<ST, CO, BX, H, RS, NT, WPE, true>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+// Wave-tiled two-step batch shapes: WT waves per block, one 64-column tile
+// each.
+template <int ST, int CO, int H, int RS, int NT, int WT>
+hipError_t go9bt2w(const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    const int blocks = (a.ntiles + WT - 1) / WT;
+    hipLaunchKernelGGL((k_d2q9_t2<ST, CO, 64, H, RS, NT, 0, true, WT>), dim3(blocks), dim3(64 * WT),
+                       WT * t2_wave_lds_bytes<T>(H, RS), s, (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+template <int ST, int CO, int H, int RS, int NT, int WT>
+hipError_t prep9bt2w()
+{
+    using T = typename Form<ST>::T;
+    constexpr size_t b = WT * t2_wave_lds_bytes<T>(H, RS);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_d2q9_t2<ST, CO, 64, H, RS, NT, 0, true, WT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+template <int ST, int CO>
+hipError_t dispatch9bt2(int v, bool prep, const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+#define LBM_BT2W(H, RS, NT, WT) return prep ? prep9bt2w<ST, CO, H, RS, NT, WT>() : go9bt2w<ST, CO, H, RS, NT, WT>(src, dst, a, s)
+    switch (v) {
+    case 12: LBM_BT2W(16, 3, 6, 4);
+    case 13: LBM_BT2W(16, 0, 6, 4);
+    default: break;
+    }
+#undef LBM_BT2W
+#define LBM_BT2(BX, H, RS, NT) return prep ? prep9bt2<ST, CO, BX, H, RS, NT>() : go9bt2<ST, CO, BX, H, RS, NT>(src, dst, a, s)
+    switch (v) {
+    case 9: LBM_BT2(64, 16, 3, 6);
+    case 10: LBM_BT2(64, 16, 0, 6);
+    case 11: LBM_BT2(256, 16, 4, 6);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBM_BT2
+}
+
 template <int ST, int CO>
 hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, hipStream_t s)
 {
@@ -1640,7 +1767,9 @@ hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, h
     case 4: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 6>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 7: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 10>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
     case 8: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 14>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
-    default: return hipErrorInvalidValue;
+    default:
+        if constexpr (CO == CO_MINXENT4) return dispatch9bt2<ST, CO>(v, false, src, dst, a, s);
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -1714,6 +1843,8 @@ hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipSt
 struct ShapeB {
     int blk, npt;
     const char *name;
+    int steps = 1;  // steps per launch
+    int rows = 0;   // two-step shapes: tile rows (tiles are blk x rows nodes of one instance)
 };
 constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "batch 128 nodes/block"},
                                 {256, 1, "batch 256 nodes/block nt-load nt-store"},
@@ -1722,7 +1853,16 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {256, 1, "batch 256 nodes/block nt-store, XCD-banded"},
                                 {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store, XCD-banded"},
                                 {256, 1, "batch 256 nodes/block nt-store prio"},
-                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store prio"}};
+                                {256, 1, "batch 256 nodes/block nt-load(unshifted planes) nt-store prio"},
+                                // two steps per launch (MinxEnt4 only)
+                                {64, 1, "batch two steps per launch, 64x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
+                                {64, 1, "batch two steps per launch, 64x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, nt-load(unshifted planes) nt-store", 2, 16},
+                                {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
+                                {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), split rings, nt-load(unshifted planes) nt-store", 2, 16}};
+// Single-step batch shapes (every collision rule); the rest of kShapesB9 are
+// two-step shapes of MinxEnt4.
+constexpr int kNumB9One = 9;
 constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "batch 128x1 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block"}, {256, 8, "batch 256x8 nodes/block"},
                                 {256, 4, "batch 256x4 nodes/block nt-load nt-store"},
@@ -1793,7 +1933,6 @@ int d2q9_variant_steps(int coll, int v)
 {
     return (coll == CO_MINXENT4 && v >= 0 && v < kNumShapes) ? kShapes[v].steps : 1;
 }
-int d2q9_odd_step_variant() { return kOddStepShape; }
 
 hipError_t prepare_d2q9_variant(int st, int coll, int v)
 {
@@ -1812,11 +1951,33 @@ int d1q3_variant_count() { return kNumShapes3; }
 const char *d1q3_variant_name(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].name : "?"; }
 constexpr int kNumB9 = sizeof(kShapesB9) / sizeof(kShapesB9[0]);
 constexpr int kNumB3 = sizeof(kShapesB3) / sizeof(kShapesB3[0]);
-int batch_variant_count(int lattice) { return lattice == 3 ? kNumB3 : kNumB9; }
+int batch_variant_count(int lattice, int coll)
+{
+    if (lattice == 3) return kNumB3;
+    return coll == CO_MINXENT4 ? kNumB9 : kNumB9One;
+}
+int batch_variant_steps(int lattice, int v)
+{
+    return (lattice == 9 && v >= 0 && v < kNumB9) ? kShapesB9[v].steps : 1;
+}
 int batch_tile_nodes(int lattice, int v)
 {
     if (lattice == 3) return (v >= 0 && v < kNumB3) ? kShapesB3[v].blk * kShapesB3[v].npt : 0;
-    return (v >= 0 && v < kNumB9) ? kShapesB9[v].blk * kShapesB9[v].npt : 0;
+    if (v < 0 || v >= kNumB9) return 0;
+    if (kShapesB9[v].steps == 2) return -(kShapesB9[v].blk * 4096 + kShapesB9[v].rows);
+    return kShapesB9[v].blk * kShapesB9[v].npt;
+}
+hipError_t prepare_batch_variant(int st, int coll, int v)
+{
+    if (coll != CO_MINXENT4 || batch_variant_steps(9, v) != 2) return hipSuccess;
+    const StepArgs none{};
+    switch (st) {
+    case ST_F64: return dispatch9bt2<ST_F64, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F32N64: return dispatch9bt2<ST_F32N64, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F32: return dispatch9bt2<ST_F32, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    case ST_F16DEV: return dispatch9bt2<ST_F16DEV, CO_MINXENT4>(v, true, nullptr, nullptr, none, nullptr);
+    default: return hipErrorInvalidValue;
+    }
 }
 const char *batch_variant_name(int lattice, int v)
 {
@@ -1839,7 +2000,7 @@ hipError_t launch_d2q9_step(int st, int coll, int v, const void *src, void *dst,
 hipError_t launch_d2q9_batch_step(int st, int coll, int v, const void *src, void *dst, const StepArgs &a,
                                   hipStream_t s)
 {
-    if (v < 0 || v >= batch_variant_count(9)) return hipErrorInvalidValue;
+    if (v < 0 || v >= batch_variant_count(9, coll)) return hipErrorInvalidValue;
     switch (st) {
     case ST_F64: return dispatch9bc<ST_F64>(coll, v, src, dst, a, s);
     case ST_F32N64: return dispatch9bc<ST_F32N64>(coll, v, src, dst, a, s);
@@ -1903,7 +2064,7 @@ hipError_t launch_d1q3_step(int st, int v, const void *src, void *dst, const Ste
 
 hipError_t launch_d1q3_batch_step(int st, int v, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
-    if (v < 0 || v >= batch_variant_count(3)) return hipErrorInvalidValue;
+    if (v < 0 || v >= batch_variant_count(3, 0)) return hipErrorInvalidValue;
     switch (st) {
     case ST_F64: return dispatch3b<ST_F64>(v, src, dst, a, s);
     case ST_F32N64: return dispatch3b<ST_F32N64>(v, src, dst, a, s);

@@ -41,7 +41,8 @@ struct StepArgs {
     DevStatus *status;      // one record per instance
     const int64_t *step_base;  // if not null, added to `step` on the error path
     const int32_t *tile_inst;  // batched: instance of each tile
-    const int32_t *tile_first; // batched: first node (D1Q3) or first row (D2Q9) of each tile
+    const int32_t *tile_first; // batched: first node of each tile, or for two-step shapes the tile's index
+                               // ty * tiles_x + tx within its instance
     int64_t step;
     int32_t bc;
     int32_t ntiles;
@@ -49,17 +50,17 @@ struct StepArgs {
     int32_t xcd_swizzle;
     float fp16_scale;       // FP16DEV: 2^k
     float fp16_iscale;      // 2^-k
+    int32_t max_steps;      // two-step shapes: steps this launch takes (1 or 2)
 };
 
 // Host-side launchers (return hipError_t of the launch).
 int d2q9_variant_count(int coll);
 const char *d2q9_variant_name(int variant);
 // Steps one launch of a single-lattice D2Q9 shape takes (1, or 2 for the
-// temporally blocked shapes), the single-step shape that takes the last step
-// of an odd count, and the host-side set-up a shape needs before its first
+// temporally blocked shapes; StepArgs::max_steps = 1 makes one of those take
+// a single step), and the host-side set-up a shape needs before its first
 // launch (call outside stream capture).
 int d2q9_variant_steps(int coll, int variant);
-int d2q9_odd_step_variant();
 hipError_t prepare_d2q9_variant(int st, int coll, int variant);
 hipError_t launch_d2q9_step(int storage, int coll, int variant, const void *src, void *dst,
                             const StepArgs &a, hipStream_t s);
@@ -76,9 +77,15 @@ hipError_t launch_d1q3_batch_step(int storage, int variant, const void *src, voi
 // final state (it may equal src).
 hipError_t launch_d2q9_lds(int storage, int coll, const void *src, void *dst, const StepArgs &a, int nsteps,
                            int block, size_t smem_bytes, hipStream_t s);
-int batch_variant_count(int lattice);
+// Batched shapes: count (MinxEnt4 D2Q9 batches also have two-step shapes),
+// steps per launch, nodes per tile of the tile table (negative for the 2D
+// tiles of a two-step shape: -(width * 4096 + rows)), name, and the
+// host-side set-up before a shape's first launch.
+int batch_variant_count(int lattice, int coll);
+int batch_variant_steps(int lattice, int variant);
 int batch_tile_nodes(int lattice, int variant);
 const char *batch_variant_name(int lattice, int variant);
+hipError_t prepare_batch_variant(int st, int coll, int variant);
 
 // Set the state of one instance: pre-shifted equilibrium of FP64 fields
 // (d_rho, d_ux, d_uy: nx*ny device doubles) or of FP64 populations (d_f:

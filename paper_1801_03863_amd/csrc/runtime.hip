@@ -216,11 +216,24 @@ int check_batch(const lbm_params_t *p, int32_t n)
 int build_tiles(lbm_ctx *c, int tile_nodes)
 {
     std::vector<int32_t> ti, tf;
-    for (int i = 0; i < c->n; ++i) {
-        const int64_t nn = (int64_t)c->inst[i].nx * c->inst[i].ny;
-        for (int64_t s = 0; s < nn; s += tile_nodes) {
-            ti.push_back(i);
-            tf.push_back((int32_t)s);
+    if (tile_nodes < 0) {
+        // Two-step shapes: tiles of bx x rows nodes, row-major within each
+        // instance, recorded as the tile's index ty * tiles_x + tx.
+        const int bx = -tile_nodes / 4096, rows = -tile_nodes % 4096;
+        for (int i = 0; i < c->n; ++i) {
+            const int64_t nt = (int64_t)((c->inst[i].nx + bx - 1) / bx) * ((c->inst[i].ny + rows - 1) / rows);
+            for (int64_t k = 0; k < nt; ++k) {
+                ti.push_back(i);
+                tf.push_back((int32_t)k);
+            }
+        }
+    } else {
+        for (int i = 0; i < c->n; ++i) {
+            const int64_t nn = (int64_t)c->inst[i].nx * c->inst[i].ny;
+            for (int64_t s = 0; s < nn; s += tile_nodes) {
+                ti.push_back(i);
+                tf.push_back((int32_t)s);
+            }
         }
     }
     if (c->d_tile_inst) (void)hipFree(c->d_tile_inst);
@@ -287,6 +300,7 @@ lbm::StepArgs step_args(const lbm_ctx *c, DevStatus *status, int64_t step, const
     a.xcd_swizzle = 0;  // launch order; each launcher sets its own
     a.fp16_scale = c->scale;
     a.fp16_iscale = c->iscale;
+    a.max_steps = 2;  // two-step shapes; lbm_step asks for one where a count is odd
     return a;
 }
 
@@ -305,16 +319,18 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
 // single-lattice D2Q9 shapes, else 1.
 int launch_steps(const lbm_ctx *c, int v)
 {
-    return (!c->batch && c->b == 9) ? lbm::d2q9_variant_steps(c->p.collision, v) : 1;
+    if (c->b != 9) return 1;
+    if (c->batch) return v == c->lds_variant ? 1 : lbm::batch_variant_steps(9, v);
+    return lbm::d2q9_variant_steps(c->p.collision, v);
 }
 
-// Launch `n` (1 or 2) steps of the context's shape from buf[cur]: the state
-// ends in buf[cur ^ 1] either way.  One step of a two-step shape runs on a
-// single-step shape.
+// Launch `n` (1 or 2) steps of shape v from buf[cur]: the state ends in
+// buf[cur ^ 1] either way (a two-step shape asked for one step takes one).
 hipError_t launch_steps_from(const lbm_ctx *c, int v, int n, int cur, const lbm::StepArgs &a, hipStream_t s)
 {
-    if (launch_steps(c, v) == 2 && n == 1) v = lbm::d2q9_odd_step_variant();
-    return launch_step(c, v, c->buf[cur], c->buf[cur ^ 1], a, s);
+    lbm::StepArgs b = a;
+    b.max_steps = n;
+    return launch_step(c, v, c->buf[cur], c->buf[cur ^ 1], b, s);
 }
 
 // Launches that replay `steps` steps with shape v, which sets how often the
@@ -326,7 +342,7 @@ int64_t launches_for(const lbm_ctx *c, int v, int64_t steps)
 
 int variant_count(const lbm_ctx *c)
 {
-    if (c->batch) return lbm::batch_variant_count(c->b) + (c->lds_variant >= 0 ? 1 : 0);
+    if (c->batch) return lbm::batch_variant_count(c->b, c->p.collision) + (c->lds_variant >= 0 ? 1 : 0);
     return c->b == 9 ? lbm::d2q9_variant_count(c->p.collision) : lbm::d1q3_variant_count();
 }
 
@@ -509,7 +525,7 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
         CK(hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         const size_t need = 2 * 9 * (size_t)maxn * c->elem;
         if (need <= (size_t)smem) {
-            c->lds_variant = lbm::batch_variant_count(9);
+            c->lds_variant = lbm::batch_variant_count(9, c->p.collision);
             c->lds_bytes = need;
             c->lds_block = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (maxn + 63) / 64 * 64));
         }
@@ -640,6 +656,8 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
     else HIPCHK(hipDeviceSynchronize());
     drop_graphs(c);
     if (!c->batch && c->b == 9) HIPCHK(lbm::prepare_d2q9_variant(c->storage, c->p.collision, v));
+    if (c->batch && c->b == 9 && v != c->lds_variant)
+        HIPCHK(lbm::prepare_batch_variant(c->storage, c->p.collision, v));
     c->variant = v;
     if (c->batch && v != c->lds_variant && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes)
         return build_tiles(c, lbm::batch_tile_nodes(c->b, v));

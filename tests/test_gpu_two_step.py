@@ -1,11 +1,14 @@
-"""Two steps per launch (the temporally blocked single-lattice D2Q9 shapes).
+"""Two steps per launch (the temporally blocked D2Q9 MinxEnt4 shapes, single
+lattices and batches).
 
 Each such launch computes one step into LDS and the next from there, so its
 results must be bitwise equal to two single-step launches: for every boundary
 kind, for lattices smaller than, equal to and ragged against one tile, for odd
-step counts (the last step then runs on a single-step shape), under graph
-replay, and with the same status records (first unstable step and node,
-guarded count), wherever the event falls inside a launch.
+step counts (the last launch then takes one step), under graph replay, and
+with the same status records (first unstable step and node, guarded count),
+wherever the event falls inside a launch.  Batches add instances of uneven
+size sharing one tile table, and per-instance step limits (in the full-size
+step-limit tests).
 """
 
 import numpy as np
@@ -114,3 +117,77 @@ def test_two_step_status_matches_oracle_wherever_the_event_falls(amp, seed, firs
             b.lbm_free(ctx)
         assert s["unstable"], v
         assert (s["first_step"], s["first_node"], s["guarded"]) == (o["first_step"], o["first_node"], o["guarded"]), v
+
+
+# --------------------------------------------------------------------------
+# Batches
+# --------------------------------------------------------------------------
+
+def _batch(b, sizes, precision="fp32_newton64", seed=41, amp=0.05, bc="cavity"):
+    rng = np.random.default_rng(seed)
+    params, rs, us, vs = [], [], [], []
+    for (nx, ny) in sizes:
+        params.append(b.make_params("d2q9", "minxent4", bc, precision, nx, ny, 0.58, 0.0, 0.1, 1.0))
+        rs.append(1.0 + 0.01 * rng.uniform(-1, 1, nx * ny))
+        us.append(amp * rng.uniform(-1, 1, nx * ny))
+        vs.append(amp * rng.uniform(-1, 1, nx * ny))
+    return params, np.concatenate(rs), np.concatenate(us), np.concatenate(vs)
+
+
+def batch_two_step_shapes(b, params, r, u, v):
+    ctx = b.lbm_init_batch(params, r, u, v)
+    try:
+        vs = [k for k in range(b.lbm_variant_count(ctx)) if b.lbm_variant_steps(ctx, k) == 2]
+    finally:
+        b.lbm_free(ctx)
+    assert vs
+    return vs
+
+
+def _run_batch(b, params, r, u, v, variant, steps, graph=0):
+    ctx = b.lbm_init_batch(params, r, u, v)
+    try:
+        b.lbm_set_variant(ctx, variant)
+        if graph:
+            b.lbm_set_graph_chunk(ctx, graph)
+        b.lbm_step(ctx, steps)
+        f = b.lbm_get_populations(ctx, 9)
+        st = [_status(s) for s in b.lbm_status_batch(ctx, len(params))]
+    finally:
+        b.lbm_free(ctx)
+    return f, st
+
+
+@pytest.mark.parametrize("precision", ["fp32_newton64", "fp64", "fp16dev"])
+def test_batch_two_step_shapes_bitwise(precision):
+    # widths below, equal to and ragged against 64, 128 and 256; a tall
+    # instance; the smallest lattice
+    sizes = [(3, 3), (64, 17), (65, 40), (130, 33), (300, 21), (7, 150), (257, 64)]
+    b = B()
+    params, r, u, v = _batch(b, sizes, precision)
+    for steps, graph in ((10, 0), (9, 0), (11, 4)):
+        ref = _run_batch(b, params, r, u, v, 0, steps, graph)
+        for k in batch_two_step_shapes(b, params, r, u, v):
+            got = _run_batch(b, params, r, u, v, k, steps, graph)
+            assert np.array_equal(got[0], ref[0]), (k, steps, graph)
+            assert got[1] == ref[1], (k, steps, graph)
+
+
+def test_batch_two_step_status_of_an_unstable_instance():
+    # one instance starts far from equilibrium and turns unstable; the others
+    # stay stable: equal status records in every shape, FP64 against the oracle
+    b = B()
+    sizes = [(40, 30), (70, 20), (33, 33)]
+    params, r, u, v = _batch(b, sizes, "fp64", bc="periodic")
+    n0 = 40 * 30
+    rr, uu, vv = smooth_fields(40, 30, seed=3, amp=0.36, rho_amp=0.2)
+    r[:n0], u[:n0], v[:n0] = rr.ravel(), uu.ravel(), vv.ravel()
+    params[0] = b.make_params("d2q9", "minxent4", "periodic", "fp64", 40, 30, 0.501, 0.0, 0.0, 1.0)
+    o = orc_run("d2q9", "minxent4", "periodic", 40, 30, 0.501, rr, uu, vv, steps=9)
+    assert o["unstable"]
+    ref = _run_batch(b, params, r, u, v, 0, 9)
+    assert ref[1][0] == (True, o["first_step"], o["first_node"], o["guarded"])
+    assert not ref[1][1][0] and not ref[1][2][0]
+    for k in batch_two_step_shapes(b, params, r, u, v):
+        got = _run_batch(b, params, r, u, v, k, 9)
+        assert got[1] == ref[1], k
