@@ -134,6 +134,8 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, gr
     variant = B.lbm_autotune(ctx, tune_cache)
     spl = B.lbm_variant_steps(ctx, variant)
     if graph_chunk > 0:
+        # a whole number of launches per graph
+        graph_chunk = -(-graph_chunk // spl) * spl
         B.lbm_set_graph_chunk(ctx, graph_chunk)
     B.lbm_step(ctx, warmup)
     torch.cuda.synchronize()
@@ -156,16 +158,27 @@ def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, gr
     del ws
     return {"wall_s": wall, "event_ms": e0.elapsed_time(e1), "variant": shape, "nodes": info["nodes"],
             "bytes_per_step": info["bytes_per_step"], "fields": {"rho": r, "ux": u, "uy": v}, "status": st,
-            "per_instance": per, "steps_per_launch": spl}
+            "per_instance": per, "steps_per_launch": spl, "graph_chunk": graph_chunk}
+
+
+def launches(steps, spl, chunk):
+    """Launches that run `steps` steps with a shape taking up to `spl` steps
+    per launch, in HIP graphs of `chunk` steps (0: plain launches)."""
+    ceil = lambda a, b: -(-a // b)
+    if chunk > 0:
+        return steps // chunk * ceil(chunk, spl) + ceil(steps % chunk, spl)
+    return ceil(steps, spl)
 
 
 def rate(res, steps):
     """MLUPS, and the algorithmic HBM rate of one launch: every stored
-    population read once and written once per launch, whether the launch
-    takes one step or two."""
+    population read once and written once per launch, whatever number of
+    steps the launch takes (the average launch time is the timed region over
+    its launches)."""
     mlups = res["nodes"] * steps / res["wall_s"] / 1e6
     spl = res["steps_per_launch"]
-    gbs = res["bytes_per_step"] / (res["event_ms"] / steps * spl * 1e-3) / 1e9
+    n = launches(steps, spl, res.get("graph_chunk", 0))
+    gbs = res["bytes_per_step"] * n / (res["event_ms"] * 1e-3) / 1e9
     return {"mlups": round(mlups, 1), "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "steps_per_launch": spl, "launch_shape": res["variant"], "unstable": res["status"]["unstable"]}
 

@@ -1480,6 +1480,142 @@ __global__ void k_clear_status(DevStatus *st, int n)
 }
 
 // --------------------------------------------------------------------------
+// D1Q3, up to K steps per launch (temporal blocking).
+//
+// A block owns S = BX * NPT consecutive nodes of one lattice (a tile-table
+// entry in a batch) and loads the stored populations of a window reaching
+// KMAX nodes further on each side into LDS: on a periodic axis the window
+// wraps (window node w is lattice node (x0 - KMAX + w) mod n, as often as the
+// window needs it); otherwise it is cut at the lattice ends.  Step s then
+// recomputes every window node that still has both neighbours from step
+// s - 1: each step the valid part shrinks by one node at every window end
+// that is not a lattice end, while at a lattice end the wall pulls from
+// itself exactly as the single-step kernels do (neighbour rule).  After k
+// steps (k <= KMAX) the block's own nodes are still valid and go to HBM.
+// Every window node is computed with the same arithmetic and rounded to the
+// storage type after every step, so results are bitwise equal to k
+// single-step launches, while HBM sees one read (plus the 2 KMAX halo) and
+// one write of every population per k steps.
+// --------------------------------------------------------------------------
+
+template <class T>
+constexpr size_t tk_lds_bytes(int s, int kmax)
+{
+    return sizeof(T) * (size_t)2 * 3 * (size_t)(s + 2 * kmax);
+}
+
+// Wave-level minimum of a 64-bit event key and one atomic for the wave.
+__device__ __forceinline__ void report_key(DevStatus *st, uint64_t key)
+{
+    if (__ballot(key != ~0ull) == 0ull) return;
+    uint32_t lo = (uint32_t)key, hi = (uint32_t)(key >> 32);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t l2 = (uint32_t)__shfl_xor((int)lo, o), h2 = (uint32_t)__shfl_xor((int)hi, o);
+        if (h2 < hi || (h2 == hi && l2 < lo)) {
+            hi = h2;
+            lo = l2;
+        }
+    }
+    if (__lane_id() == 0) {
+        atomicOr(&st->flags, 1u);
+        atomicMin((unsigned long long *)&st->first, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
+template <int ST, int BX, int NPT, int KMAX, int NT = 0, bool BATCH = false>
+__global__ __launch_bounds__(BX) void k_d1q3_tk(const typename Form<ST>::T *__restrict__ src_all,
+                                                typename Form<ST>::T *__restrict__ dst_all, StepArgs a)
+{
+    using C = typename Form<ST>::C;
+    using T = typename Form<ST>::T;
+    constexpr int S = BX * NPT;
+    constexpr int W = S + 2 * KMAX;
+    extern __shared__ __align__(16) unsigned char tk_lds[];
+    T *b0 = (T *)tk_lds;  // two buffers of [3][W]
+    T *b1 = b0 + 3 * W;
+    const int tile = (int)blockIdx.x;
+    const int ii = BATCH ? a.tile_inst[tile] : 0;
+    const Inst &in = BATCH ? a.inst[ii] : a.one;
+    const int n = in.nx;
+    const int64_t P = in.plane;
+    const int x0 = BATCH ? a.tile_first[tile] : tile * S;  // first own node
+    const T *src = src_all + (BATCH ? in.offset : 0);
+    T *dst = dst_all + (BATCH ? in.offset : 0);
+    DevStatus *status = a.status + ii;
+    const bool wrap = a.bc == BC_PERIODIC;
+    const int t = (int)threadIdx.x;
+    const int sn = min(S, n - x0);  // own nodes (block-uniform)
+
+    // Steps this launch takes here (block-uniform): a.max_steps (<= KMAX),
+    // fewer for a batch instance that reaches its step limit, none for one
+    // that has (it carries its nodes over).
+    const int64_t s0 = a.step + (a.step_base ? *a.step_base : 0);
+    int kdo = min(a.max_steps, KMAX);  // the window holds KMAX steps
+    if constexpr (BATCH) kdo = (int)max((int64_t)0, min((int64_t)kdo, in.stop - s0));
+    if (kdo <= 0) {
+        for (int k = t; k < sn; k += BX) carry_node(src, dst, P, 3, x0 + k);
+        return;
+    }
+
+    // Window [wl, wl + L) in lattice coordinates (mod n when periodic).
+    const int wl = wrap ? x0 - KMAX : max(0, x0 - KMAX);
+    const int wr = wrap ? x0 + sn + KMAX : min(n, x0 + sn + KMAX);
+    const int L = wr - wl;
+    const bool lend = !wrap && wl == 0;  // the window's left end is the lattice's
+    const bool rend = !wrap && wr == n;
+    auto lattice_x = [&](int w) {
+        int x = wl + w;
+        if (wrap) x = ((x % n) + n) % n;
+        return x;
+    };
+    for (int w = t; w < L; w += BX) {
+        const int x = lattice_x(w);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b0[q * W + w] = ldraw<T, (NT & 1) != 0>(src + q * P + x);
+    }
+    const C r0 = C(2.0 / 3.0) * C(in.rho0), r1 = C(1.0 / 6.0) * C(in.rho0);
+    const C omega = C(in.omega);
+    const int own0 = x0 - wl;  // window index of the first own node
+    uint64_t first_bad = ~0ull;
+    T *cur = b0, *nxt = b1;
+    for (int s = 1; s <= kdo; ++s) {
+        lds_barrier();
+        const int lo = lend ? 0 : s, hi = rend ? L : L - s;
+        for (int w = lo + t; w < hi; w += BX) {
+            const int wm = (lend && w == 0) ? w : w - 1;
+            const int wp = (rend && w == L - 1) ? w : w + 1;
+            C f0 = load<ST>(&cur[w], r0, a.fp16_iscale);
+            C fp = load<ST>(&cur[W + wm], r1, a.fp16_iscale);
+            C fm = load<ST>(&cur[2 * W + wp], r1, a.fp16_iscale);
+            // Walls exist only without wrap, where lattice x = wl + w.
+            const int role = (!wrap && (wl + w == 0 || wl + w == n - 1)) ? R_WALL : R_FLUID;
+            const int fl = node3<C>(f0, fp, fm, role, omega);
+            if (fl && w >= own0 && w < own0 + sn) {
+                const uint64_t key = event_key(s0 + s - 1, x0 + (w - own0));
+                first_bad = key < first_bad ? key : first_bad;
+            }
+            nxt[w] = to_storage<ST>(f0, r0, a.fp16_scale);
+            nxt[W + w] = to_storage<ST>(fp, r1, a.fp16_scale);
+            nxt[2 * W + w] = to_storage<ST>(fm, r1, a.fp16_scale);
+        }
+        T *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    lds_barrier();
+    for (int k = t; k < sn; k += BX) {
+        const int w = own0 + k;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if constexpr ((NT & 2) != 0) __builtin_nontemporal_store(cur[q * W + w], dst + q * P + x0 + k);
+            else dst[q * P + x0 + k] = cur[q * W + w];
+        }
+    }
+    report_key(status, first_bad);
+}
+
+// --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
 
@@ -1790,6 +1926,7 @@ hipError_t dispatch9bc(int coll, int v, const void *src, void *dst, const StepAr
 struct Shape3 {
     int bx, npt;
     const char *name;
+    int steps = 1;  // steps per launch (at most)
 };
 constexpr Shape3 kShapes3[] = {
     {256, 1, "256 nodes=1"},
@@ -1800,8 +1937,56 @@ constexpr Shape3 kShapes3[] = {
     {256, 8, "256 groups of 8 nodes, 16-byte vectors"},
     {256, 8, "256 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
     {128, 8, "128 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
+    {256, 4, "1024-node segments in LDS, up to 16 steps per launch", 16},
+    {256, 4, "1024-node segments in LDS, up to 32 steps per launch, nt-load nt-store", 32},
+    {256, 4, "1024-node segments in LDS, up to 64 steps per launch, nt-load nt-store", 64},
+    {128, 8, "1024-node segments in LDS (128 threads), up to 32 steps per launch, nt-load nt-store", 32},
+    {256, 4, "1024-node segments in LDS, up to 256 steps per launch, nt-load nt-store", 256},
+    {1024, 1, "1024-node segments in LDS (1024 threads), up to 256 steps per launch, nt-load nt-store", 256},
 };
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
+
+// K-step D1Q3 launches: one block per S-node segment (a single lattice's
+// segments in order, or a batch's tile table).
+template <int ST, int BX, int NPT, int KMAX, int NT, bool BATCH>
+hipError_t go3tk(const void *src, void *dst, const StepArgs &a, hipStream_t s)
+{
+    using T = typename Form<ST>::T;
+    constexpr int S = BX * NPT;
+    const int blocks = BATCH ? a.ntiles : (a.one.nx + S - 1) / S;
+    hipLaunchKernelGGL((k_d1q3_tk<ST, BX, NPT, KMAX, NT, BATCH>), dim3(blocks), dim3(BX), tk_lds_bytes<T>(S, KMAX), s,
+                       (const T *)src, (T *)dst, a);
+    return hipGetLastError();
+}
+
+// LDS beyond the default 64 KiB must be allowed before the first launch
+// (outside any stream capture): the 256-step window in FP64 needs it.
+template <int ST, int BX, int NPT, int KMAX, int NT, bool BATCH>
+hipError_t prep3tk()
+{
+    using T = typename Form<ST>::T;
+    constexpr size_t b = tk_lds_bytes<T>(BX * NPT, KMAX);
+    if (b <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_d1q3_tk<ST, BX, NPT, KMAX, NT, BATCH>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+
+template <int ST, bool BATCH>
+hipError_t dispatch3tk(int k, const void *src, void *dst, const StepArgs &a, hipStream_t s, bool prep = false)
+{
+#define LBM_TK(BX, NPT, K, NT) \
+    return prep ? prep3tk<ST, BX, NPT, K, NT, BATCH>() : go3tk<ST, BX, NPT, K, NT, BATCH>(src, dst, a, s)
+    switch (k) {
+    case 0: LBM_TK(256, 4, 16, 0);
+    case 1: LBM_TK(256, 4, 32, 3);
+    case 2: LBM_TK(256, 4, 64, 3);
+    case 3: LBM_TK(128, 8, 32, 3);
+    case 4: LBM_TK(256, 4, 256, 3);
+    case 5: LBM_TK(1024, 1, 256, 3);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBM_TK
+}
 
 template <int ST, int BX, int NT = 0>
 hipError_t go3v(const void *src, void *dst, const StepArgs &a, hipStream_t s)
@@ -1834,7 +2019,7 @@ hipError_t dispatch3(int v, const void *src, void *dst, const StepArgs &a, hipSt
     case 5: return go3v<ST, 256>(src, dst, a, s);
     case 6: return go3v<ST, 256, 3>(src, dst, a, s);
     case 7: return go3v<ST, 128, 3>(src, dst, a, s);
-    default: return hipErrorInvalidValue;
+    default: return dispatch3tk<ST, false>(v - 8, src, dst, a, s);
     }
 }
 
@@ -1870,16 +2055,24 @@ constexpr ShapeB kShapesB3[] = {{256, 1, "batch 256x1 nodes/block"}, {128, 1, "b
                                 {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
                                 {128, 8, "batch 128 groups of 8 nodes, 16-byte vectors nt-load nt-store"},
                                 {128, 1, "batch 128x1 nodes/block, XCD-banded"},
-                                {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors, XCD-banded"}};
+                                {256, 8, "batch 256 groups of 8 nodes, 16-byte vectors, XCD-banded"},
+                                {256, 4, "batch 1024-node segments in LDS, up to 16 steps per launch", 16},
+                                {256, 4, "batch 1024-node segments in LDS, up to 32 steps per launch, nt-load nt-store", 32},
+                                {256, 4, "batch 1024-node segments in LDS, up to 64 steps per launch, nt-load nt-store", 64},
+                                {128, 8, "batch 1024-node segments in LDS (128 threads), up to 32 steps per launch, nt-load nt-store", 32},
+                                {256, 4, "batch 1024-node segments in LDS, up to 256 steps per launch, nt-load nt-store", 256},
+                                {1024, 1, "batch 1024-node segments in LDS (1024 threads), up to 256 steps per launch, nt-load nt-store", 256}};
 
 template <int ST>
 hipError_t dispatch3b(int v, const void *src, void *dst, const StepArgs &a_in, hipStream_t s)
 {
     using T = typename Form<ST>::T;
     // Tiles run in launch order; shapes 8 and 9 are 1 and 5 with tiles in
-    // XCD-banded order instead (measured slower, kept as candidates).
+    // XCD-banded order instead (measured slower, kept as candidates); 10 on
+    // take up to K steps per launch.
     StepArgs a = a_in;
     a.xcd_swizzle = 0;
+    if (v >= 10) return dispatch3tk<ST, true>(v - 10, src, dst, a, s);
     if (v >= 8) {
         a.xcd_swizzle = 1;
         v = v == 8 ? 1 : 5;
@@ -1958,7 +2151,27 @@ int batch_variant_count(int lattice, int coll)
 }
 int batch_variant_steps(int lattice, int v)
 {
-    return (lattice == 9 && v >= 0 && v < kNumB9) ? kShapesB9[v].steps : 1;
+    if (lattice == 3) return (v >= 0 && v < kNumB3) ? kShapesB3[v].steps : 1;
+    return (v >= 0 && v < kNumB9) ? kShapesB9[v].steps : 1;
+}
+int d1q3_variant_steps(int v) { return (v >= 0 && v < kNumShapes3) ? kShapes3[v].steps : 1; }
+
+hipError_t prepare_d1q3_variant(int st, int batch, int v)
+{
+    const int k = v - (batch ? 10 : 8);  // index among the K-step shapes
+    if (k < 0) return hipSuccess;
+    const StepArgs none{};
+    switch (st) {
+    case ST_F64: return batch ? dispatch3tk<ST_F64, true>(k, nullptr, nullptr, none, nullptr, true)
+                              : dispatch3tk<ST_F64, false>(k, nullptr, nullptr, none, nullptr, true);
+    case ST_F32N64: return batch ? dispatch3tk<ST_F32N64, true>(k, nullptr, nullptr, none, nullptr, true)
+                                 : dispatch3tk<ST_F32N64, false>(k, nullptr, nullptr, none, nullptr, true);
+    case ST_F32: return batch ? dispatch3tk<ST_F32, true>(k, nullptr, nullptr, none, nullptr, true)
+                              : dispatch3tk<ST_F32, false>(k, nullptr, nullptr, none, nullptr, true);
+    case ST_F16DEV: return batch ? dispatch3tk<ST_F16DEV, true>(k, nullptr, nullptr, none, nullptr, true)
+                                 : dispatch3tk<ST_F16DEV, false>(k, nullptr, nullptr, none, nullptr, true);
+    default: return hipErrorInvalidValue;
+    }
 }
 int batch_tile_nodes(int lattice, int v)
 {

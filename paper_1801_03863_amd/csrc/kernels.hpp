@@ -50,7 +50,7 @@ struct StepArgs {
     int32_t xcd_swizzle;
     float fp16_scale;       // FP16DEV: 2^k
     float fp16_iscale;      // 2^-k
-    int32_t max_steps;      // two-step shapes: steps this launch takes (1 or 2)
+    int32_t max_steps;      // shapes taking several steps per launch: steps this launch takes
 };
 
 // Host-side launchers (return hipError_t of the launch).
@@ -68,6 +68,8 @@ hipError_t launch_d2q9_batch_step(int storage, int coll, int variant, const void
                                   const StepArgs &a, hipStream_t s);
 int d1q3_variant_count();
 const char *d1q3_variant_name(int variant);
+int d1q3_variant_steps(int variant);  // steps one launch takes at most (K-step shapes; StepArgs::max_steps sets fewer)
+hipError_t prepare_d1q3_variant(int st, int batch, int variant);  // host-side set-up before the first launch
 hipError_t launch_d1q3_step(int storage, int variant, const void *src, void *dst, const StepArgs &a,
                             hipStream_t s);
 hipError_t launch_d1q3_batch_step(int storage, int variant, const void *src, void *dst,

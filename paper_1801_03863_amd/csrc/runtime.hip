@@ -300,7 +300,7 @@ lbm::StepArgs step_args(const lbm_ctx *c, DevStatus *status, int64_t step, const
     a.xcd_swizzle = 0;  // launch order; each launcher sets its own
     a.fp16_scale = c->scale;
     a.fp16_iscale = c->iscale;
-    a.max_steps = 2;  // two-step shapes; lbm_step asks for one where a count is odd
+    a.max_steps = 2;  // launchers of multi-step shapes set the count they need
     return a;
 }
 
@@ -315,17 +315,17 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
     return lbm::launch_d1q3_step(c->storage, variant, src, dst, a, s);
 }
 
-// Steps one launch of shape v takes: 2 for the temporally blocked
-// single-lattice D2Q9 shapes, else 1.
+// Steps one launch of shape v takes at most: 2 for the temporally blocked
+// D2Q9 shapes, up to 64 for the K-step D1Q3 shapes, else 1.
 int launch_steps(const lbm_ctx *c, int v)
 {
-    if (c->b != 9) return 1;
+    if (c->b != 9) return c->batch ? lbm::batch_variant_steps(3, v) : lbm::d1q3_variant_steps(v);
     if (c->batch) return v == c->lds_variant ? 1 : lbm::batch_variant_steps(9, v);
     return lbm::d2q9_variant_steps(c->p.collision, v);
 }
 
-// Launch `n` (1 or 2) steps of shape v from buf[cur]: the state ends in
-// buf[cur ^ 1] either way (a two-step shape asked for one step takes one).
+// Launch `n` steps (at most the shape's steps per launch) of shape v from
+// buf[cur]: the state ends in buf[cur ^ 1] whatever n is.
 hipError_t launch_steps_from(const lbm_ctx *c, int v, int n, int cur, const lbm::StepArgs &a, hipStream_t s)
 {
     lbm::StepArgs b = a;
@@ -337,7 +337,8 @@ hipError_t launch_steps_from(const lbm_ctx *c, int v, int n, int cur, const lbm:
 // two buffers swap.
 int64_t launches_for(const lbm_ctx *c, int v, int64_t steps)
 {
-    return launch_steps(c, v) == 2 ? steps / 2 + (steps & 1) : steps;
+    const int64_t k = launch_steps(c, v);
+    return (steps + k - 1) / k;
 }
 
 int variant_count(const lbm_ctx *c)
@@ -658,6 +659,7 @@ int lbm_set_variant(lbm_ctx_t *c, int32_t v)
     if (!c->batch && c->b == 9) HIPCHK(lbm::prepare_d2q9_variant(c->storage, c->p.collision, v));
     if (c->batch && c->b == 9 && v != c->lds_variant)
         HIPCHK(lbm::prepare_batch_variant(c->storage, c->p.collision, v));
+    if (c->b == 3) HIPCHK(lbm::prepare_d1q3_variant(c->storage, c->batch, v));
     c->variant = v;
     if (c->batch && v != c->lds_variant && lbm::batch_tile_nodes(c->b, v) != c->tile_nodes)
         return build_tiles(c, lbm::batch_tile_nodes(c->b, v));
@@ -766,7 +768,7 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
             } else {
                 for (int r = 0; r < n; ++r) {
                     lbm::StepArgs a = step_args(c, c->d_status_scratch, 0, nullptr);
-                    HIPCHK(launch_step(c, v, c->buf[c->cur], c->buf[c->cur ^ 1], a, c->stream));
+                    HIPCHK(launch_steps_from(c, v, spl, c->cur, a, c->stream));
                 }
             }
             HIPCHK(hipEventRecord(e1, c->stream));

@@ -508,7 +508,9 @@ def test_batch_step_limits_d2q9(graph):
 
 def test_batch_step_limits_d1q3():
     b = B()
-    _limits_case(b, "d1q3", [100, 1000, 2500, 37], [3, 10, 0, -1], [0, 1, 5, 8], 0)
+    # (10 and 12 take up to 16 and 64 steps per launch: the limits fall inside
+    # a launch)
+    _limits_case(b, "d1q3", [100, 1000, 2500, 37], [3, 10, 0, -1], [0, 1, 5, 8, 10, 12], 0)
     ctx = b.lbm_init_batch([b.make_params("d1q3", "srt", "tube", "fp64", 50, 1, 0.7)] * 2,
                            np.ones(100), np.zeros(100), None)
     try:

@@ -1,5 +1,6 @@
-"""Two steps per launch (the temporally blocked D2Q9 MinxEnt4 shapes, single
-lattices and batches).
+"""Several steps per launch: the temporally blocked D2Q9 MinxEnt4 shapes (two
+steps, single lattices and batches) and the D1Q3 shapes that keep 1024-node
+segments in LDS for up to 16, 32 or 64 steps.
 
 Each such launch computes one step into LDS and the next from there, so its
 results must be bitwise equal to two single-step launches: for every boundary
@@ -8,12 +9,14 @@ step counts (the last launch then takes one step), under graph replay, and
 with the same status records (first unstable step and node, guarded count),
 wherever the event falls inside a launch.  Batches add instances of uneven
 size sharing one tile table, and per-instance step limits (in the full-size
-step-limit tests).
+step-limit tests).  D1Q3 adds periodic lattices narrower than a segment's
+window, which then wraps several times.
 """
 
 import numpy as np
 import pytest
 
+from paper_1801_03863_amd import inputs as I
 from tests.gpu_helpers import B, field_errors, fluid_mask, gpu_run, orc_run, smooth_fields
 
 pytestmark = pytest.mark.gpu
@@ -191,3 +194,94 @@ def test_batch_two_step_status_of_an_unstable_instance():
     for k in batch_two_step_shapes(b, params, r, u, v):
         got = _run_batch(b, params, r, u, v, k, 9)
         assert got[1] == ref[1], k
+
+
+# --------------------------------------------------------------------------
+# D1Q3, up to K steps per launch
+# --------------------------------------------------------------------------
+
+def d1q3_k_step_shapes(b, batch=False):
+    p = b.make_params("d1q3", "srt", "tube", "fp64", 50, 1, 0.7)
+    ctx = (b.lbm_init_batch([p, p], np.ones(100), np.zeros(100), None) if batch
+           else b.lbm_init(p, np.ones(50), np.zeros(50), None))
+    try:
+        vs = [k for k in range(b.lbm_variant_count(ctx)) if b.lbm_variant_steps(ctx, k) > 2]
+    finally:
+        b.lbm_free(ctx)
+    assert vs
+    return vs
+
+
+@pytest.mark.parametrize("bc", ["tube", "periodic", "cavity"])
+@pytest.mark.parametrize("precision", ["fp64", "fp16dev"])
+def test_d1q3_k_step_shapes_bitwise(bc, precision):
+    # lattices shorter than, equal to and ragged against a 1024-node segment;
+    # periodic lattices narrower than the window; step counts below, at and
+    # above each shape's steps per launch
+    b = B()
+    rng = np.random.default_rng(5)
+    for n in (3, 100, 1024, 1025, 5000):
+        rho = 1.0 + 0.3 * rng.uniform(-1, 1, n)
+        ux = 0.1 * rng.uniform(-1, 1, n)
+        for steps in (1, 15, 16, 17, 70):
+            ref = gpu_run("d1q3", "srt", bc, precision, n, 1, 0.6, rho, ux, steps=steps, variant=0, want_f=True)
+            for v in d1q3_k_step_shapes(b):
+                g = gpu_run("d1q3", "srt", bc, precision, n, 1, 0.6, rho, ux, steps=steps, variant=v, want_f=True)
+                assert np.array_equal(g["f"], ref["f"]), (n, steps, v)
+                assert _status(g["status"]) == _status(ref["status"]), (n, steps, v)
+
+
+@pytest.mark.parametrize("chunk", [5, 16, 40])
+def test_d1q3_k_step_graph_replay_is_bitwise(chunk):
+    n = 3000
+    rho, ux = I.tube_fields(n, 2.0, 0.75)
+    ref = gpu_run("d1q3", "srt", "tube", "fp32", n, 1, 0.52, rho, ux, steps=123, variant=0, want_f=True)
+    for v in d1q3_k_step_shapes(B()):
+        g = gpu_run("d1q3", "srt", "tube", "fp32", n, 1, 0.52, rho, ux, steps=123, variant=v, graph=chunk,
+                    want_f=True)
+        assert np.array_equal(g["f"], ref["f"]), (chunk, v)
+
+
+@pytest.mark.parametrize("ratio,tau,first", [(4.0, 0.5001, 12), (3.0, 0.505, 127), (6.0, 0.501, 1)])
+def test_d1q3_k_step_status_matches_oracle(ratio, tau, first):
+    # 300-node shock tubes that turn unstable at steps 12, 127 and 1 (found
+    # with the oracle): every K-step shape reports the oracle's first step and
+    # node, wherever in a launch the step falls
+    n = 300
+    rho, ux = I.tube_fields(n, ratio * 0.75, 0.75)
+    o = orc_run("d1q3", "srt", "tube", n, 1, tau, rho, ux, steps=200)
+    assert o["unstable"] and o["first_step"] == first
+    for v in d1q3_k_step_shapes(B()):
+        g = gpu_run("d1q3", "srt", "tube", "fp64", n, 1, tau, rho, ux, steps=200, variant=v)
+        assert g["status"]["unstable"], v
+        assert (g["status"]["first_step"], g["status"]["first_node"]) == (o["first_step"], o["first_node"]), v
+
+
+def test_d1q3_k_step_batch_bitwise():
+    b = B()
+    rng = np.random.default_rng(6)
+    sizes = [3, 500, 1024, 1500, 4097, 64]
+    params, rs, us = [], [], []
+    for n in sizes:
+        params.append(b.make_params("d1q3", "srt", "tube", "fp64", n, 1, 0.55, 0.0, 0.0, 1.0))
+        rs.append(1.0 + 0.3 * rng.uniform(-1, 1, n))
+        us.append(0.1 * rng.uniform(-1, 1, n))
+    r, u = np.concatenate(rs), np.concatenate(us)
+
+    def run(v, steps, graph=0):
+        ctx = b.lbm_init_batch(params, r, u, None)
+        try:
+            b.lbm_set_variant(ctx, v)
+            if graph:
+                b.lbm_set_graph_chunk(ctx, graph)
+            b.lbm_step(ctx, steps)
+            return b.lbm_get_populations(ctx, 3), [_status(s) for s in b.lbm_status_batch(ctx, len(params))]
+        finally:
+            b.lbm_free(ctx)
+
+    for steps, graph in ((33, 0), (64, 0), (45, 20)):
+        ref = run(0, steps, graph)
+        for v in d1q3_k_step_shapes(b, batch=True):
+            got = run(v, steps, graph)
+            assert np.array_equal(got[0], ref[0]), (v, steps, graph)
+            assert got[1] == ref[1], (v, steps, graph)

@@ -168,3 +168,62 @@ def test_two_step_indexing_equals_two_single_steps(rs, bc):
         f = rng.random((9, ny, nx)).astype(np.float32)
         assert np.array_equal(two_steps(f, nx, ny, bc, bx, h, rs), one_step(one_step(f, nx, ny, bc), nx, ny, bc)), \
             (nx, ny, bx, h)
+
+
+# --------------------------------------------------------------------------
+# D1Q3, up to K steps per launch: the window of each segment, its shrinking
+# valid part, and the wall's pull from itself at a lattice end.
+# --------------------------------------------------------------------------
+
+def d1q3_collide(f0, fp, fm, wall):
+    if wall:
+        return f0, fm, fp
+    s = f0 + fp + fm
+    return (np.float32(f0 + 0.1 * np.sin(s)), np.float32(fp + 0.1 * np.sin(2 * s + fm)),
+            np.float32(fm + 0.1 * np.sin(3 * s - fp)))
+
+
+def d1q3_one_step(f, n, wrap):
+    g = np.empty_like(f)
+    for x in range(n):
+        xm = x - 1 if x > 0 else (n - 1 if wrap else 0)
+        xp = x + 1 if x < n - 1 else (0 if wrap else n - 1)
+        g[:, x] = d1q3_collide(f[0, x], f[1, xm], f[2, xp], (not wrap) and x in (0, n - 1))
+    return g
+
+
+def d1q3_k_steps(f, n, wrap, seg, kmax, k):
+    out = np.full_like(f, np.nan)
+    for x0 in range(0, n, seg):
+        sn = min(seg, n - x0)
+        wl = x0 - kmax if wrap else max(0, x0 - kmax)
+        wr = x0 + sn + kmax if wrap else min(n, x0 + sn + kmax)
+        L = wr - wl
+        lend, rend = (not wrap) and wl == 0, (not wrap) and wr == n
+        cur = np.array([f[:, (wl + w) % n] for w in range(L)], dtype=np.float32).T
+        for s in range(1, k + 1):
+            nxt = np.full_like(cur, np.nan)
+            lo, hi = (0 if lend else s), (L if rend else L - s)
+            for w in range(lo, hi):
+                wm = w if (lend and w == 0) else w - 1
+                wp = w if (rend and w == L - 1) else w + 1
+                vals = (cur[0, w], cur[1, wm], cur[2, wp])
+                assert not np.isnan(vals).any(), ("invalid window node read", x0, s, w)
+                nxt[:, w] = d1q3_collide(*vals, (not wrap) and (wl + w) in (0, n - 1))
+            cur = nxt
+        own0 = x0 - wl
+        out[:, x0:x0 + sn] = cur[:, own0:own0 + sn]
+    return out
+
+
+@pytest.mark.parametrize("wrap", [False, True])
+def test_d1q3_k_step_indexing_equals_single_steps(wrap):
+    rng = np.random.default_rng(11)
+    # segments shorter than, equal to and ragged against the lattice; windows
+    # wider than a periodic lattice (several wraps); k below and at kmax
+    for n, seg, kmax, k in [(3, 4, 2, 2), (10, 4, 3, 3), (10, 4, 3, 1), (17, 8, 5, 4), (5, 2, 6, 6), (40, 16, 4, 4)]:
+        f = rng.random((3, n)).astype(np.float32)
+        ref = f
+        for _ in range(k):
+            ref = d1q3_one_step(ref, n, wrap)
+        assert np.array_equal(d1q3_k_steps(f, n, wrap, seg, kmax, k), ref), (n, seg, kmax, k)
