@@ -148,8 +148,10 @@ int lbm_step(lbm_ctx_t *ctx, int64_t nsteps);
  * lbm_info reports them); from then on its state is carried over unchanged
  * and lbm_moments returns it as it was after that step.  A negative entry,
  * or stop_steps == NULL, removes the limits.  n must equal the number of
- * instances.  Works with graph replay and the LDS-resident shape.
- * LBM_EINVAL for a single-lattice context.  Synchronises. */
+ * instances.  Works with graph replay, the LDS-resident shape and shapes
+ * that take several steps per launch (a limit inside a launch ends that
+ * instance's steps there).  LBM_EINVAL for a single-lattice context.
+ * Synchronises. */
 int lbm_set_batch_steps(lbm_ctx_t *ctx, const int64_t *stop_steps, int32_t n);
 
 /* Replay time steps from a captured HIP graph of `chunk` steps (chunk >= 1;
@@ -196,13 +198,15 @@ int lbm_set_variant(lbm_ctx_t *ctx, int32_t variant);
 int lbm_variant_count(const lbm_ctx_t *ctx);
 const char *lbm_variant_name(const lbm_ctx_t *ctx, int32_t variant);
 
-/* Steps one launch of a shape takes: 1, or 2 for the temporally blocked
- * shapes of a single D2Q9 lattice (MinxEnt4), which compute one step into
- * on-chip memory and the next from there, so that HBM sees one read and one
- * write of every population per two steps.  Their results are bitwise equal
- * to single steps; lbm_step() runs an odd count's last step, and a graph
- * chunk's, on a single-step shape.  0 if ctx is NULL or variant out of
- * range. */
+/* Steps one launch of a shape takes at most: 1; 2 for the temporally blocked
+ * D2Q9 shapes (MinxEnt4, single lattices and batches), which compute one
+ * step into on-chip memory and the next from there; 16, 32, 64 or 256 for
+ * the D1Q3 shapes that keep 1024-node segments on chip for that many steps.
+ * HBM then sees one read and one write of every population per launch.
+ * Results are bitwise equal to single steps, status records included;
+ * lbm_step() and graph chunks run a remainder as a launch of fewer steps,
+ * and a batch instance's step limit can end its steps inside a launch.  0 if
+ * ctx is NULL or variant out of range. */
 int lbm_variant_steps(const lbm_ctx_t *ctx, int32_t variant);
 
 /* Write rho, ux, uy of the current state (Sec. II.A moments of the

@@ -247,8 +247,9 @@ def lbm_variant_name(ctx, v):
 
 
 def lbm_variant_steps(ctx, v):
-    """Steps one launch of shape v takes (1, or 2 for the temporally blocked
-    single-lattice D2Q9 shapes)."""
+    """Steps one launch of shape v takes at most (1; 2 for the temporally
+    blocked D2Q9 shapes; up to 256 for the D1Q3 shapes that keep segments on
+    chip)."""
     return _lib.lbm_variant_steps(ctx, int(v))
 
 
