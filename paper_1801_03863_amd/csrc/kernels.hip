@@ -13,11 +13,14 @@
 // element and every write is aligned and unit-stride.  Planes follow each
 // other at a stride of the node count rounded up to 64 elements, plus, for a
 // large single lattice, a tuned pad that is a multiple of 256 bytes, so every
-// plane starts 256-byte aligned.  Populations are read
-// and written exactly once per step.  The kernels are bound by HBM bandwidth
-// in FP64, FP32 and FP32-storage/FP64-compute forms, and by VALU issue (the
+// plane starts 256-byte aligned.  The single-step kernels read and write
+// every population exactly once per step; they are bound by HBM bandwidth in
+// the FP64, FP32 and FP32-storage/FP64-compute forms, and by VALU issue (the
 // logarithms, reciprocals and 4 x 4 solve of the Newton step) when the
-// populations are FP16 deviations.
+// populations are FP16 deviations.  The multi-step kernels further down (two
+// D2Q9 steps, or up to 256 D1Q3 steps, per launch) keep the steps between in
+// LDS and read and write every population once per launch; HBM then no
+// longer bounds them.
 //
 // Slots of boundary nodes whose upstream node lies outside the lattice read a
 // clamped (in-bounds) location; their values are bounced outward and never
