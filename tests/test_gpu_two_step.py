@@ -213,7 +213,7 @@ def d1q3_k_step_shapes(b, batch=False):
 
 
 @pytest.mark.parametrize("bc", ["tube", "periodic", "cavity"])
-@pytest.mark.parametrize("precision", ["fp64", "fp16dev"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_newton64", "fp16dev"])
 def test_d1q3_k_step_shapes_bitwise(bc, precision):
     # lattices shorter than, equal to and ragged against a 1024-node segment;
     # periodic lattices narrower than the window; step counts below, at and
