@@ -573,6 +573,18 @@ static void fluid_collide(const orc_params *P, const double *f, double *out, orc
     }
 }
 
+/* The fluid collision a whole run applies at one node under P (lattice,
+ * collision rule, tau, tau2), exposed so that the tests can pin each rule's
+ * relaxation rates (Table III) without a run.  b = 9 (D2Q9) or 3 (D1Q3)
+ * populations in and out.  Returns 1 if the MinxEnt start point was guarded,
+ * else 0. */
+int orc_collide_node(const orc_params *P, const double *f, double *out)
+{
+    orc_status st = {0, -1, 0, -1};
+    fluid_collide(P, f, out, &st);
+    return st.guarded != 0;
+}
+
 /* Run `steps` time steps on the window [x0, x0+wx) x [y0, y0+wy) of the
  * nx x ny lattice described by P, starting from the equilibrium of the given
  * fields (arrays of wx*wy values, x fastest; uy ignored for D1Q3).  Node roles

@@ -86,6 +86,8 @@ def _load():
         lib.orc_collide_mrt_d2q9.argtypes = [_D, _D, _D]
         lib.orc_collide_srt_d1q3.argtypes = [_D, ctypes.c_double, _D]
         lib.orc_collide_moment_d1q3.argtypes = [_D, ctypes.c_double, _D]
+        lib.orc_collide_node.argtypes = [ctypes.POINTER(Params), _D, _D]
+        lib.orc_collide_node.restype = ctypes.c_int
         lib.orc_run_window.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, _D, _D, _D, ctypes.c_int64, _D, _D, _D, _D,
                                        ctypes.POINTER(Status)]
@@ -176,6 +178,16 @@ def collide_moment_d1q3(f, tau):
     out = np.zeros(3)
     _load().orc_collide_moment_d1q3(_ptr(_vec(f, 3)), tau, _ptr(out))
     return out
+
+
+def collide_node(collision, f, tau, tau2=0.0, lattice=D2Q9):
+    """The fluid collision a whole run applies at one node (rule, tau, tau2);
+    returns (f_post, guarded)."""
+    b = 3 if lattice == D1Q3 else 9
+    P = Params(lattice, collision, BC_PERIODIC, 0, 3, 1 if lattice == D1Q3 else 3, tau, tau2, 0.0, 1.0)
+    out = np.zeros(b)
+    g = _load().orc_collide_node(ctypes.byref(P), _ptr(_vec(f, b)), _ptr(out))
+    return out, bool(g)
 
 
 def run(lattice, collision, bc, nx, ny, tau, rho, ux, uy=None, steps=1, tau2=0.0, u_lid=0.0,
