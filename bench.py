@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update: nine populations read once and written
+# once per step, at the stored width.
+BYTES_PER_LU = {"fp64": 144, "fp32": 72, "fp32_newton64": 72, "fp16dev": 36}
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
 # second (one wave64 VALU instruction is 64 lane-operations issued over four
 # cycles); equal to the FP64 vector FMA rate, 78.6 TFLOP/s / 2.
@@ -88,9 +91,30 @@ def fluid_errors(a, b, n):
     return out
 
 
-def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_cache, force_variant=None):
+def settle_clocks(B, torch, ctx, spl, seconds):
+    """Untimed launches of the context's own shape for about `seconds` of wall
+    time, so that the timed steps start at the clock the card holds under this
+    load (the first launches after idle run while the clock ramps up; under
+    sustained FP64 work it then settles at the power limit).  Whole launches
+    only, so the state the timed region starts from is a valid step count.
+    Returns (settle seconds, settle steps)."""
+    if seconds <= 0:
+        return (0.0, 0)
+    chunk = 64 * spl
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        B.lbm_step(ctx, chunk)
+        torch.cuda.synchronize()
+        done += chunk
+    return (round(time.perf_counter() - t0, 3), done)
+
+
+def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_cache, force_variant=None,
+              settle_s=0.0):
     """Autotune (or read the cache), optionally replace the chosen shape by
-    force_variant (the tuned plane pad stays), then time `steps` steps."""
+    force_variant (the tuned plane pad stays), settle the clock for settle_s
+    seconds of untimed launches, then time `steps` steps."""
     p = B.make_params("d2q9", "minxent4", "cavity", precision, n, n, tau, 0.0, u_lid, 1.0)
     ws = torch.empty(B.lbm_workspace_bytes(p), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
@@ -102,6 +126,7 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
     spl = B.lbm_variant_steps(ctx, variant)
     B.lbm_step(ctx, warmup)
     torch.cuda.synchronize()
+    settle = settle_clocks(B, torch, ctx, spl, settle_s)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -122,7 +147,7 @@ def time_form(B, torch, precision, n, tau, u_lid, fields, steps, warmup, tune_ca
     del ws
     return {"wall_s": wall, "event_ms": ev_ms, "variant": shape, "steps_per_launch": spl,
             "nodes": info["nodes"], "bytes_per_step": info["bytes_per_step"],
-            "fields": {"rho": r, "ux": u, "uy": v}, "status": st}
+            "fields": {"rho": r, "ux": u, "uy": v}, "status": st, "settle": settle}
 
 
 def time_batch(B, torch, params, rho, ux, uy, steps, warmup, tune_cache=None, graph_chunk=0):
@@ -171,15 +196,18 @@ def launches(steps, spl, chunk):
 
 
 def rate(res, steps):
-    """MLUPS, and the algorithmic HBM rate of one launch: every stored
-    population read once and written once per launch, whatever number of
-    steps the launch takes (the average launch time is the timed region over
-    its launches)."""
+    """MLUPS; the algorithmic HBM rate (every stored population read once and
+    written once per step, over the event time of the timed steps); and the
+    per-launch rate (one read and one write per launch, whatever number of
+    steps the launch takes: the bytes HBM must move)."""
     mlups = res["nodes"] * steps / res["wall_s"] / 1e6
     spl = res["steps_per_launch"]
     n = launches(steps, spl, res.get("graph_chunk", 0))
     gbs = res["bytes_per_step"] * n / (res["event_ms"] * 1e-3) / 1e9
-    return {"mlups": round(mlups, 1), "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+    # the method's bytes: every population read and written once per step
+    alg = res["bytes_per_step"] * steps / (res["event_ms"] * 1e-3) / 1e9
+    return {"mlups": round(mlups, 1), "alg_gbs": round(alg, 1), "alg_hbm_frac": round(alg / HBM_PEAK_GBS, 4),
+            "per_launch_gbs": round(gbs, 1), "per_launch_hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "steps_per_launch": spl, "launch_shape": res["variant"], "unstable": res["status"]["unstable"]}
 
 
@@ -334,10 +362,94 @@ def copy_bandwidth(B, torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes / ms / 1e6
 
 
-def cpu_baseline(n, tau, u_lid, seed, rows=512, steps=8):
+ORACLE_WINDOW_CHILD = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_1801_03863_amd import inputs as I
+n, y0, rows, steps, tau, u_lid, seed = (int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]), int(sys.argv[5]),
+                                        float(sys.argv[6]), float(sys.argv[7]), int(sys.argv[8]))
+r, u, v = I.cavity_fields_window(n, 0, y0, n, rows, 1.0, seed)
+w = (0, y0, n, rows)
+t0 = time.perf_counter()
+O.run(O.D2Q9, O.MINXENT4, O.BC_CAVITY, n, n, tau, r, u, v, steps=0, u_lid=u_lid, window=w)
+t1 = time.perf_counter()
+O.run(O.D2Q9, O.MINXENT4, O.BC_CAVITY, n, n, tau, r, u, v, steps=steps, u_lid=u_lid, window=w)
+t2 = time.perf_counter()
+print(max((t2 - t1) - (t1 - t0), 1e-9))
+"""
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_all_cores(n, tau, u_lid, seed, steps=8):
+    """One single-threaded oracle process per usable host core (at most 16,
+    the host share of one GPU), each over its own block of rows of the same
+    cavity.  The processes are children started fresh (no fork of this
+    process, which holds the GPU); each times its own run minus a zero-step
+    run of its window.  Aggregate MLUPS = all lattice updates / the slowest
+    child's time."""
+    import subprocess
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    rows = max(1, min(256, n // cores))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", ORACLE_WINDOW_CHILD, ROOT, str(n), str(k * rows), str(rows),
+                               str(steps), repr(tau), repr(u_lid), str(seed)],
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, env=env, text=True)
+             for k in range(cores)]
+    secs = []
+    for p in procs:
+        o, e = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("oracle child failed: " + e[-400:])
+        secs.append(float(o.strip().splitlines()[-1]))
+    lu = n * rows * steps * cores
+    return {"value": round(lu / max(secs) / 1e6, 4), "unit": "MLUPS", "cores": cores,
+            "cpu_model": host_cpu_model(), "nproc": os.cpu_count(),
+            "sample": "%d processes, rows [%d k, %d k + %d) of the %dx%d cavity (k = process), %d steps each, "
+                      "FP64 single-threaded C oracle per process; init subtracted; slowest process %.2f s"
+                      % (cores, rows, rows, rows, n, n, steps, max(secs))}
+
+
+def oracle_tube_800():
+    """The 800-node D1Q3 shock tube (tau 0.51, 400 steps), whole, in the oracle."""
+    from oracle import oracle as O
+    from paper_1801_03863_amd import inputs as I
+    c = I.shock_tube_800()
+    t0 = time.perf_counter()
+    O.run(O.D1Q3, O.SRT, O.BC_TUBE, c["nx"], 1, c["tau"], c["rho"], c["ux"], steps=c["steps"])
+    secs = time.perf_counter() - t0
+    return {"value": round(c["nx"] * c["steps"] / secs / 1e6, 3), "unit": "MLUPS", "seconds": round(secs, 4),
+            "cores": 1, "sample": "whole run, %d nodes x %d steps" % (c["nx"], c["steps"])}
+
+
+def oracle_cavity_256_stored():
+    """The oracle time of the whole 256^2, 20000-step cavity, stored when the
+    golden file of the full-length parity test was written (one core of the
+    machine that wrote it, not this host)."""
+    path = os.path.join(ROOT, "tests", "golden", "cavity256_re1000_20000.json")
+    with open(path) as fh:
+        g = json.load(fh)
+    n, steps, secs = g["n"], g["steps"], g["oracle_seconds"]
+    return {"value": round(n * n * steps / secs / 1e6, 3), "unit": "MLUPS", "seconds": secs, "cores": 1,
+            "sample": "whole run, %dx%d x %d steps; stored in tests/golden (measured when it was written, "
+                      "on the build host)" % (n, n, steps)}
+
+
+def cpu_baseline(n, tau, u_lid, seed, rows=512, steps=8, all_cores=True):
     """The FP64 oracle, single-threaded, on rows [0, rows) of the same cavity
     (bottom wall included) for `steps` steps; init and read-back cost removed
-    by subtracting a zero-step run of the same window."""
+    by subtracting a zero-step run of the same window.  Beside it: the
+    all-cores figure, the whole 800-node tube, and the stored 256^2 time."""
     from oracle import oracle as O
     from paper_1801_03863_amd import inputs as I
     r, u, v = I.cavity_fields_window(n, 0, 0, n, rows, 1.0, seed)
@@ -349,9 +461,15 @@ def cpu_baseline(n, tau, u_lid, seed, rows=512, steps=8):
     O.run(O.D2Q9, O.MINXENT4, O.BC_CAVITY, n, n, tau, r, u, v, steps=steps, u_lid=u_lid, window=(0, 0, n, rows))
     t_run = time.perf_counter() - t0
     secs = max(t_run - t_init, 1e-9)
-    return {"value": round(n * rows * steps / secs / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "rows 0-%d of the %dx%d cavity (full width, bottom wall included), %d steps, "
-                      "FP64 single-threaded C oracle; init/read-back subtracted" % (rows - 1, n, n, steps)}
+    out = {"value": round(n * rows * steps / secs / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "cpu_model": host_cpu_model(),
+           "sample": "rows 0-%d of the %dx%d cavity (full width, bottom wall included), %d steps, "
+                     "FP64 single-threaded C oracle; init/read-back subtracted" % (rows - 1, n, n, steps)}
+    if all_cores:
+        out["all_cores"] = oracle_all_cores(n, tau, u_lid, seed, steps)
+    out["tube800_full"] = oracle_tube_800()
+    out["cavity256_20000_stored"] = oracle_cavity_256_stored()
+    return out
 
 
 def main():
@@ -359,6 +477,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--settle", type=float, default=0.5,
+                    help="seconds of untimed headline launches before its timed steps")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -387,14 +507,25 @@ def main():
     tau = I.tau_from_re(cfg["u_lid"], n, cfg["re"])
     fields = I.cavity_fields(n, 1.0, cfg["seed"])
 
-    head = time_form(B, torch, "fp32_newton64", n, tau, cfg["u_lid"], fields, args.steps, args.warmup,
-                     args.tune_cache)
+    head_form = "fp32_newton64"
+    head = time_form(B, torch, head_form, n, tau, cfg["u_lid"], fields, args.steps, args.warmup,
+                     args.tune_cache, settle_s=args.settle)
+    settle_s, settle_steps = head["settle"]
     nodes = head["nodes"]
     spl = head["steps_per_launch"]
-    ms_event = head["event_ms"] / args.steps  # per step
-    ms_launch = ms_event * spl                # the timed steps are a whole number of launches
+    n_launch = launches(args.steps, spl, 0)
+    ms_launch = head["event_ms"] / n_launch   # HIP events on the context's stream over the timed launches
     value = nodes * args.steps / head["wall_s"] / 1e6
-    hbm_achieved = head["bytes_per_step"] / (ms_launch * 1e-3) / 1e9
+    lu_per_launch = nodes * args.steps / n_launch
+    # Per-launch HBM view: one read and one write of every stored population
+    # per launch, whatever number of steps the launch takes.
+    per_launch_bytes = head["bytes_per_step"]
+    per_launch_gbs = per_launch_bytes / (ms_launch * 1e-3) / 1e9
+    # The HBM roofline of the method's work: 72 B per lattice update (every
+    # population read and written once per step, FP32 storage) times the
+    # lattice updates one launch performs, over the launch time.
+    alg_bytes = BYTES_PER_LU[head_form] * lu_per_launch
+    alg_gbs = alg_bytes / (ms_launch * 1e-3) / 1e9
 
     out = {
         "metric": "MLUPS and % of HBM roofline, FP64 vs FP32/batched at stated field error",
@@ -407,7 +538,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 storage, f64 compute",
+        "dtype": "f32 storage, f64 compute (refinements stopped four orders below the f32 rounding: "
+                 "hardware reciprocal for the 4x4 pivots, log series truncated at 2^-42)",
         "data": "synthetic (seeded noise on rho0=1, fluid at rest)",
         "config": {"workload": "d2q9 lid-driven cavity %dx%d, MinxEnt4, lid 0.05, Re 5000, tau %.5f, seed %d"
                                % (n, n, tau, cfg["seed"]),
@@ -415,23 +547,32 @@ def main():
     }
     digest = kernel_source_digest()
     traffic = read_traffic(digest)
-    hbm = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-           "algorithmic_bytes_per_launch": head["bytes_per_step"], "kernel_ms_per_launch": round(ms_launch, 5),
-           "steps_per_launch": spl}
-    if spl == 1:
-        out["roofline"] = hbm
-    else:
-        # Two steps per launch halve the HBM bytes per step; the kernel is then
-        # bound by VALU issue.  Lane-operations per node and step come from
-        # the committed counter summary of the same kernel sources.
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(alg_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(alg_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "algorithmic_bytes_per_launch": int(alg_bytes), "bytes_per_lattice_update": BYTES_PER_LU[head_form],
+        "lattice_updates_per_launch": int(lu_per_launch), "kernel_ms_per_launch": round(ms_launch, 5),
+        "steps_per_launch": spl, "launches_timed": n_launch,
+        # One read and one write of every stored population per launch: the
+        # bytes HBM must move when a launch takes several steps.
+        "per_launch_hbm": {"bytes": per_launch_bytes, "achieved": round(per_launch_gbs, 1),
+                           "frac": round(per_launch_gbs / HBM_PEAK_GBS, 4)},
+    }
+    if spl > 1:
+        # Several steps per launch cut the HBM bytes per step; what binds the
+        # kernel is then VALU issue.  Lane-operations per node and step come
+        # from the committed counter summary of the same kernel sources.
         valu = read_valu(digest)
-        alu = None if valu is None else valu * nodes * spl / (ms_launch * 1e-3) / 1e12
-        out["roofline"] = {"bound": "alu", "achieved": None if alu is None else round(alu, 3),
-                           "peak": round(VALU_PEAK_TOPS, 3), "unit": "T VALU lane-ops/s",
-                           "frac": None if alu is None else round(alu / VALU_PEAK_TOPS, 4), "traffic": traffic,
-                           "valu_lane_ops_per_node_step": valu, "kernel_ms_per_launch": round(ms_launch, 5),
-                           "steps_per_launch": spl, "hbm": hbm}
+        alu = None if valu is None else valu * lu_per_launch / (ms_launch * 1e-3) / 1e12
+        out["roofline"]["binding_roof"] = "valu"
+        out["roofline"]["valu"] = {"achieved": None if alu is None else round(alu, 3),
+                                   "peak": round(VALU_PEAK_TOPS, 3), "unit": "T VALU lane-ops/s",
+                                   "frac": None if alu is None else round(alu / VALU_PEAK_TOPS, 4),
+                                   "lane_ops_per_lattice_update": valu}
+    else:
+        out["roofline"]["binding_roof"] = "hbm"
+    out["settle"] = {"seconds": settle_s, "steps": settle_steps,
+                     "note": "untimed launches of the headline shape before its timed steps"}
     out["status"] = head["status"]
     # The best single-step shape on the same lattice, the fused kernel as a
     # pure HBM stream (one read and one write of every population per step).
@@ -439,7 +580,10 @@ def main():
                        args.tune_cache, force_variant=SINGLE_STEP_SHAPE)
     out["single_step_fused_kernel"] = rate(single, args.extra_steps)
     if not args.no_fp64:
-        ref = time_form(B, torch, "fp64", n, tau, cfg["u_lid"], fields, args.steps, args.warmup, args.tune_cache)
+        # Same step count as the headline (its settle steps run as warm-up
+        # here), so that the fields compare at the same time step.
+        ref = time_form(B, torch, "fp64", n, tau, cfg["u_lid"], fields, args.steps, args.warmup + settle_steps,
+                        args.tune_cache)
         fp64_mlups = nodes * args.steps / ref["wall_s"] / 1e6
         out["fp64"] = rate(ref, args.steps)
         out["fp64"]["speedup_of_headline"] = round(value / fp64_mlups, 3)
