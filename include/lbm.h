@@ -139,8 +139,10 @@ int lbm_init_batch(const lbm_params_t *p, int32_t n, const double *rho, const do
                    const double *uy, void *dev_workspace, size_t ws_bytes, void *hip_stream,
                    lbm_ctx_t **out);
 
-/* Enqueue nsteps time steps (collide and stream at every node) on the
- * context's stream and return without waiting.  nsteps >= 0. */
+/* Enqueue nsteps time steps on the context's stream and return without
+ * waiting.  One step is the cycle of Sec. II.A: every node applies its role
+ * (fluid collision, bounce-back wall, equilibrium lid; Sec. IV.E), then the
+ * post-collision populations stream to the neighbours.  nsteps >= 0. */
 int lbm_step(lbm_ctx_t *ctx, int64_t nsteps);
 
 /* Per-instance step counts of a batch: instance i takes no step once the
@@ -241,6 +243,35 @@ int lbm_info(const lbm_ctx_t *ctx, int64_t *steps_done, int64_t *nodes, int64_t 
 
 /* Destroy a context; NULL-safe; never frees caller memory.  Synchronises. */
 void lbm_free(lbm_ctx_t *ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): run one
+ * single lattice from initial fields to final fields with no allocation of
+ * any kind.  The two population buffers and the status record live in a
+ * fixed device array of LBM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends.
+ *   p:             one parameter record, as for lbm_init (no batches).
+ *   rho, ux, uy:   DEVICE arrays of nx*ny doubles, the initial fields; uy is
+ *                  ignored and may be NULL for D1Q3.  Every node starts at the
+ *                  polynomial equilibrium of its fields, lid nodes at the lid
+ *                  equilibrium (the state lbm_init sets).
+ *   nsteps:        steps to run (>= 0), in the one-step launch shape 0.
+ *   rho_out, ux_out, uy_out: DEVICE arrays of nx*ny doubles receiving the
+ *                  moments of the final state, as lbm_moments writes them;
+ *                  any may be NULL; they may alias the inputs.
+ *   status:        HOST record of the run's status, or NULL.  If not NULL the
+ *                  call waits for the stream; otherwise it only enqueues work.
+ *   hip_stream:    hipStream_t as void*, NULL for the default stream.
+ * Results are bitwise those of lbm_init + lbm_step + lbm_moments with the
+ * same parameters.  A lattice needing more than LBM_NOALLOC_SCRATCH_BYTES
+ * (256 + 2 * b * round_up(nx*ny, 64) * bytes per population) is rejected
+ * with LBM_EINVAL before any work is enqueued.  Every call on one GPU shares
+ * that GPU's array and leaves its state there: calls that overlap on one GPU
+ * (two streams, or two threads) race and must be serialised by the caller. */
+#define LBM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int lbm_run_noalloc(const lbm_params_t *p, const double *rho, const double *ux, const double *uy,
+                    int64_t nsteps, double *rho_out, double *ux_out, double *uy_out,
+                    lbm_status_t *status, void *hip_stream);
 
 /* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16; 0 is a
  * no-op) on hip_stream: a reference for achievable HBM bandwidth.  Each thread

@@ -105,6 +105,7 @@ _sig("lbm_reset_status", ctypes.c_int, [_V])
 _sig("lbm_info", ctypes.c_int, [_V, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)])
 _sig("lbm_free", None, [_V])
 _sig("lbm_copy_kernel", ctypes.c_int, [_V, _V, ctypes.c_size_t, _V])
+_sig("lbm_run_noalloc", ctypes.c_int, [_P, _V, _V, _V, _I64, _V, _V, _V, ctypes.POINTER(lbm_status_t), _V])
 _sig("lbm_last_error", ctypes.c_char_p, [])
 _sig("lbm_strerror", ctypes.c_char_p, [ctypes.c_int])
 
@@ -307,6 +308,21 @@ def lbm_free(ctx):
 def lbm_copy_kernel(dst, src, nbytes, stream=None):
     _check(_lib.lbm_copy_kernel(_ptr_or_none(dst), _ptr_or_none(src), int(nbytes), _stream_handle(stream)),
            "lbm_copy_kernel")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def lbm_run_noalloc(params, rho, ux, uy, nsteps, rho_out, ux_out, uy_out, want_status=True, stream=None):
+    """One single-lattice run with no allocation: fields in and out are torch
+    float64 CUDA tensors of nx*ny values (uy / uy_out may be None for D1Q3).
+    Returns the status dict (waits for the stream) or None."""
+    st = lbm_status_t() if want_status else None
+    rc = _lib.lbm_run_noalloc(ctypes.byref(params), _ptr_or_none(rho), _ptr_or_none(ux), _ptr_or_none(uy),
+                              int(nsteps), _ptr_or_none(rho_out), _ptr_or_none(ux_out), _ptr_or_none(uy_out),
+                              ctypes.byref(st) if st is not None else None, _stream_handle(stream))
+    _check(rc, "lbm_run_noalloc")
+    return _status_dict(st) if st is not None else None
 
 
 def library_path():

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -553,6 +554,36 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     return LBM_OK;
 }
 
+// Device memory of the no-allocation entry point lbm_run_noalloc: a status
+// record (the first 256 bytes) and the two population buffers of a lattice
+// that fits.  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses this name as an address: it takes the
+// per-device address from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ENODEV, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(LBM_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -950,6 +981,80 @@ int lbm_info(const lbm_ctx_t *c, int64_t *steps_done, int64_t *nodes, int64_t *b
 }
 
 void lbm_free(lbm_ctx_t *c) { destroy(c); }
+
+int lbm_run_noalloc(const lbm_params_t *p, const double *rho, const double *ux, const double *uy, int64_t nsteps,
+                    double *rho_out, double *ux_out, double *uy_out, lbm_status_t *status, void *hip_stream)
+{
+    if (!p || !rho || !ux) return fail(LBM_EINVAL, "p, rho and ux are required");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int b = p->lattice == LBM_D1Q3 ? 3 : 9;
+    if (b == 9 && !uy) return fail(LBM_EINVAL, "uy is required for D2Q9");
+    // One instance laid out without a plane pad (the pad only moves planes;
+    // results do not depend on it).
+    std::vector<Inst> inst;
+    int64_t elems = 0, nodes = 0;
+    layout(p, 1, /*no plane pad=*/1, b, &inst, &elems, &nodes);
+    const size_t elem = elem_bytes(p->precision);
+    const size_t bb = buffer_bytes(elems, elem);
+    const size_t need = 256 + 2 * bb;
+    if (need > (size_t)LBM_NOALLOC_SCRATCH_BYTES) {
+        std::snprintf(g_err, sizeof(g_err),
+                      "lattice needs %zu bytes of scratch; lbm_run_noalloc holds %zu (use lbm_init for larger ones)",
+                      need, (size_t)LBM_NOALLOC_SCRATCH_BYTES);
+        return LBM_EINVAL;
+    }
+    std::string arch;
+    rc = check_device(&arch);
+    if (rc) return rc;
+    void *base = nullptr;
+    rc = scratch_address(&base);
+    if (rc) return rc;
+    DevStatus *st = (DevStatus *)base;
+    char *buf[2] = {(char *)base + 256, (char *)base + 256 + bb};
+    const int storage = storage_of(p->precision);
+    const int k = p->fp16_exp ? p->fp16_exp : 14;
+    const float scale = std::ldexp(1.0f, k), iscale = std::ldexp(1.0f, -k);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // The scratch keeps the previous call's contents: the status record is
+    // cleared by a kernel (no memset node under graph capture) and the
+    // initial state overwrites the first buffer.
+    HIPCHK(lbm::launch_clear_status(st, 1, s));
+    HIPCHK(lbm::launch_init(b, storage, inst[0], p->bc, rho, ux, b == 9 ? uy : nullptr, nullptr, buf[0], scale, s));
+    lbm::StepArgs a{};
+    a.inst = nullptr;
+    a.one = inst[0];
+    a.status = st;
+    a.step_base = nullptr;
+    a.bc = p->bc;
+    a.fp16_scale = scale;
+    a.fp16_iscale = iscale;
+    a.max_steps = 1;
+    int cur = 0;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        a.step = i;
+        // Shape 0: one step per launch, every node once per step.
+        hipError_t e = (b == 9) ? lbm::launch_d2q9_step(storage, p->collision, 0, buf[cur], buf[cur ^ 1], a, s)
+                                : lbm::launch_d1q3_step(storage, 0, buf[cur], buf[cur ^ 1], a, s);
+        if (e != hipSuccess) return hip_fail(e, "lbm_run_noalloc step");
+        cur ^= 1;
+    }
+    HIPCHK(lbm::launch_gather(b, storage, inst[0], p->bc, buf[cur], rho_out, ux_out, b == 9 ? uy_out : nullptr,
+                              nullptr, iscale, s));
+    if (status) {
+        DevStatus h{};
+        HIPCHK(hipMemcpyAsync(&h, st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        status->flags = h.flags;
+        status->reserved = 0;
+        const bool none = h.first == ~0ull;
+        status->first_step = none ? -1 : (int64_t)(h.first >> 32);
+        status->first_node = none ? -1 : (int64_t)(h.first & 0xffffffffull);
+        status->guarded = h.guarded;
+    }
+    return LBM_OK;
+}
 
 int lbm_copy_kernel(void *dst, const void *src, size_t bytes, void *stream)
 {

@@ -114,3 +114,20 @@ def test_batch_needs_an_instance(B):
     with pytest.raises(B.LbmError) as ei:
         B.lbm_workspace_bytes_batch([])
     assert ei.value.code == B.LBM_EINVAL
+
+
+def test_noalloc_rejects_oversize_and_bad_arguments_before_device_work(B):
+    # Checked on the host before any device call, so this runs without a GPU.
+    p = B.make_params("d2q9", "minxent4", "cavity", "fp64", 1024, 1024, 0.6, 0.0, 0.05, 1.0)
+    lib = B._lib
+    st = B.lbm_status_t()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the call fails first
+    rc = lib.lbm_run_noalloc(ctypes.byref(p), fake, fake, fake, 5, fake, fake, fake, ctypes.byref(st), None)
+    assert rc == B.LBM_EINVAL and b"scratch" in lib.lbm_last_error()
+    rc = lib.lbm_run_noalloc(ctypes.byref(p), fake, fake, fake, -1, fake, fake, fake, None, None)
+    assert rc == B.LBM_EINVAL
+    rc = lib.lbm_run_noalloc(ctypes.byref(p), None, fake, fake, 1, fake, fake, fake, None, None)
+    assert rc == B.LBM_EINVAL
+    q = B.make_params("d2q9", "minxent4", "cavity", "fp64", 64, 64, 0.5, 0.0, 0.05, 1.0)  # tau <= 1/2
+    rc = lib.lbm_run_noalloc(ctypes.byref(q), fake, fake, fake, 1, fake, fake, fake, None, None)
+    assert rc == B.LBM_EINVAL
