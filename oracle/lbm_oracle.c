@@ -509,6 +509,9 @@ typedef struct {
     int32_t first_step; /* step of the first such event, -1 if none */
     int64_t guarded;    /* node-steps where the Newton start point left p > 0 */
     int64_t first_node; /* smallest node index x + y*nx (whole lattice) unstable at first_step, -1 if none */
+    double min_post;    /* smallest fluid post-collision population over the steps up to and including
+                           first_step (the whole run if stable); -inf for a non-finite one.  A record of
+                           how close a run came to the stability criterion of Sec. IV.G, not part of it. */
 } orc_status;
 
 /* Node role from its global coordinates.  Tube: walls at x = 0 and x = nx-1
@@ -580,7 +583,7 @@ static void fluid_collide(const orc_params *P, const double *f, double *out, orc
  * else 0. */
 int orc_collide_node(const orc_params *P, const double *f, double *out)
 {
-    orc_status st = {0, -1, 0, -1};
+    orc_status st = {0, -1, 0, -1, 0.0};
     fluid_collide(P, f, out, &st);
     return st.guarded != 0;
 }
@@ -620,6 +623,7 @@ int orc_run_window(const orc_params *P, int x0, int y0, int wx, int wy,
     st->first_step = -1;
     st->first_node = -1;
     st->guarded = 0;
+    st->min_post = INFINITY;
     double flid[9];
     orc_feq_d2q9(P->rho0, P->u_lid, 0.0, flid);
 
@@ -647,6 +651,11 @@ int orc_run_window(const orc_params *P, int x0, int y0, int wx, int wy,
             for (int a = 0; a < b; ++a) loc[a] = f[a * n + i];
             if (role[i] == ROLE_FLUID) {
                 fluid_collide(P, loc, out, st);
+                if (!st->unstable || st->first_step == (int32_t)s)
+                    for (int a = 0; a < b; ++a) {
+                        double v = isfinite(out[a]) ? out[a] : -INFINITY;
+                        if (v < st->min_post) st->min_post = v;
+                    }
                 for (int a = 0; a < b; ++a)
                     if (!(out[a] >= 0.0) || !isfinite(out[a])) {
                         /* nodes are visited in increasing index, so the first one

@@ -59,6 +59,7 @@ class Status(ctypes.Structure):
         ("first_step", ctypes.c_int32),
         ("guarded", ctypes.c_int64),
         ("first_node", ctypes.c_int64),
+        ("min_post", ctypes.c_double),
     ]
 
 
@@ -218,7 +219,7 @@ def run(lattice, collision, bc, nx, ny, tau, rho, ux, uy=None, steps=1, tau2=0.0
     shape = (wx,) if lattice == D1Q3 else (wy, wx)
     out = {"rho": ro.reshape(shape), "ux": uo.reshape(shape), "uy": vo.reshape(shape),
            "unstable": bool(st.unstable), "first_step": st.first_step, "first_node": st.first_node,
-           "guarded": st.guarded}
+           "guarded": st.guarded, "min_post": st.min_post}
     if want_f:
         out["f"] = fo.reshape((b,) + shape)
     return out
