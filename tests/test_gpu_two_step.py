@@ -1,6 +1,6 @@
 """Several steps per launch: the temporally blocked D2Q9 MinxEnt4 shapes (two
 steps, single lattices and batches) and the D1Q3 shapes that keep 1024-node
-segments in LDS for up to 16, 32 or 64 steps.
+segments in LDS for up to 16, 32, 64 or 256 steps.
 
 Each such launch computes one step into LDS and the next from there, so its
 results must be bitwise equal to two single-step launches: for every boundary
@@ -197,7 +197,7 @@ def test_batch_two_step_status_of_an_unstable_instance():
 
 
 # --------------------------------------------------------------------------
-# D1Q3, up to K steps per launch
+# D1Q3, up to K steps per launch (K = 16, 32, 64 or 256)
 # --------------------------------------------------------------------------
 
 def d1q3_k_step_shapes(b, batch=False):
@@ -223,7 +223,9 @@ def test_d1q3_k_step_shapes_bitwise(bc, precision):
     for n in (3, 100, 1024, 1025, 5000):
         rho = 1.0 + 0.3 * rng.uniform(-1, 1, n)
         ux = 0.1 * rng.uniform(-1, 1, n)
-        for steps in (1, 15, 16, 17, 70):
+        # 256 and 300 steps on the longest lattice: the deepest window shrink
+        # of the 256-step shape inside one launch, on several segments
+        for steps in (1, 15, 16, 17, 70) + ((256, 300) if n == 5000 else ()):
             ref = gpu_run("d1q3", "srt", bc, precision, n, 1, 0.6, rho, ux, steps=steps, variant=0, want_f=True)
             for v in d1q3_k_step_shapes(b):
                 g = gpu_run("d1q3", "srt", bc, precision, n, 1, 0.6, rho, ux, steps=steps, variant=v, want_f=True)
@@ -279,7 +281,7 @@ def test_d1q3_k_step_batch_bitwise():
         finally:
             b.lbm_free(ctx)
 
-    for steps, graph in ((33, 0), (64, 0), (45, 20)):
+    for steps, graph in ((33, 0), (64, 0), (45, 20), (300, 0), (600, 256)):
         ref = run(0, steps, graph)
         for v in d1q3_k_step_shapes(b, batch=True):
             got = run(v, steps, graph)
