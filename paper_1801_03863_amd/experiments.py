@@ -107,16 +107,32 @@ def run_cavity_steady(n=257, re=1000.0, u_lid=0.1, rho0=2.7, precision="fp64", c
 # Sec. IV.G: stability study
 # --------------------------------------------------------------------------
 
-def stability_sweep(collision, inv_taus, lids, n=17, rho0=2.7, steps=1000, precision="fp64"):
+def tau2_of(tau, rule="printed"):
+    """The second relaxation time of the heat-flux moments (MinxEnt2, TRT,
+    MRT).  'printed': (8 tau - 1)/(2 tau - 1) as Sec. IV.C prints it;
+    'luo': (8 tau - 1)/(8 (2 tau - 1)), the rate 8(2 - s)/(8 - s) with
+    s = 1/tau of the MRT literature the paper cites for Table III, a factor 8
+    apart from the printed one."""
+    if rule == "printed":
+        return (8.0 * tau - 1.0) / (2.0 * tau - 1.0)
+    if rule == "luo":
+        return (8.0 * tau - 1.0) / (8.0 * (2.0 * tau - 1.0))
+    raise ValueError(rule)
+
+
+def stability_sweep(collision, inv_taus, lids, n=17, rho0=2.7, steps=1000, precision="fp64", tau2_rule="printed"):
     """Run one n x n cavity per (1/tau, lid speed) pair, all in one batched
     context, for `steps` steps from rest at density rho0.  A run is stable if
     every post-collision population stayed finite and non-negative (the
-    criterion of Sec. IV.G).  Returns (stable[len(inv_taus), len(lids)],
-    first_step array, max stable lid speed per 1/tau scanning downwards)."""
+    criterion of Sec. IV.G).  tau2 follows `tau2_rule` (see tau2_of).
+    Returns (stable[len(inv_taus), len(lids)], first_step array, max stable
+    lid speed per 1/tau scanning downwards)."""
     params = []
     for it in inv_taus:
         for u in lids:
-            params.append(B.make_params("d2q9", collision, "cavity", precision, n, n, 1.0 / it, 0.0, u, rho0))
+            tau = 1.0 / it
+            params.append(B.make_params("d2q9", collision, "cavity", precision, n, n, tau, tau2_of(tau, tau2_rule),
+                                        u, rho0))
     m = len(params)
     rho = np.full(m * n * n, rho0)
     z = np.zeros(m * n * n)

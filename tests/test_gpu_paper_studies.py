@@ -78,6 +78,16 @@ def sweep():
     return out
 
 
+@pytest.fixture(scope="module")
+def sweep_luo():
+    # The same sweep with tau2 = (8 tau - 1)/(8 (2 tau - 1)), the other reading
+    # of the tau2 relation (R2); SRT and MinxEnt4 do not use tau2.
+    out = {}
+    for coll in ("trt", "mrt", "minxent2"):
+        out[coll] = E().stability_sweep(coll, INV, LIDS, tau2_rule="luo")
+    return out
+
+
 def test_stability_ranking_near_zero_viscosity(sweep):
     mx = {c: v[2] for c, v in sweep.items()}
     print({c: dict(zip(INV.tolist(), m.tolist())) for c, m in mx.items()}, flush=True)
@@ -86,6 +96,23 @@ def test_stability_ranking_near_zero_viscosity(sweep):
     assert mx["minxent4"][k] > mx["mrt"][k] > mx["minxent2"][k] > mx["trt"][k] > mx["srt"][k]
     for c in ("srt", "trt", "mrt", "minxent2"):
         assert np.all(mx["minxent4"] >= mx[c]), c
+
+
+@pytest.mark.parametrize("reading", ["printed", "luo"])
+def test_stability_claims_at_every_viscosity(sweep, sweep_luo, reading):
+    # Sec. IV.G results: MinxEnt4 consistently at least as stable as MRT, and
+    # MinxEnt2 consistently at least as stable as its counterpart TRT, at
+    # every 1/tau of the sweep under either reading of tau2.  (That SRT is the
+    # least stable holds only near zero viscosity, 1/tau = 1.99, under either
+    # reading: see the previous test.)
+    mx = {c: v[2] for c, v in sweep.items()}
+    if reading == "luo":
+        mx.update({c: v[2] for c, v in sweep_luo.items()})
+    print(reading, {c: m.tolist() for c, m in mx.items()}, flush=True)
+    assert np.all(mx["minxent4"] >= mx["mrt"])
+    assert np.all(mx["minxent2"] >= mx["trt"])
+    k = int(np.where(INV == 1.99)[0][0])
+    assert mx["srt"][k] < min(mx[c][k] for c in ("trt", "mrt", "minxent2", "minxent4"))
 
 
 @pytest.mark.parametrize("coll", ["srt", "mrt", "minxent4"])
