@@ -36,8 +36,8 @@ BYTES_PER_LU = {"fp64": 144, "fp32": 72, "fp32_newton64": 72, "fp16dev": 36}
 # second (one wave64 VALU instruction is 64 lane-operations issued over four
 # cycles); equal to the FP64 vector FMA rate, 78.6 TFLOP/s / 2.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_d2q9_fp32n64_cavity4096.txt")
-PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_d2q9_cavity4096.txt")
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_fused_kernels_bench_workloads.txt")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "valu_fused_kernels_bench_workloads.txt")
 # The single-step shape quoted beside a two-step headline: 256 x 1 tiles,
 # non-temporal loads of the unshifted planes and non-temporal stores, an
 # 8-wave register budget, raised issue priority while the loads issue.

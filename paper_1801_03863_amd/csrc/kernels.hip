@@ -812,7 +812,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         ty = k / tiles_x;
         tx = k - ty * tiles_x;
     } else {
-        tile_of_block(0, a.tiles_x, tx, ty);
+        tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
     }
     const T *src = src_all + (BATCH ? in.offset : 0);
     T *dst = dst_all + (BATCH ? in.offset : 0);
@@ -1671,6 +1671,9 @@ constexpr Shape kShapes[] = {
     {256, 24, 1, 0, "two steps per launch, 256x24 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2},
     {512, 16, 1, 0, "two steps per launch, 512x16 tiles, nt-load(unshifted planes) nt-store", 2},
     {256, 16, 1, 0, "two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2},
+    {256, 32, 1, 0, "two steps per launch, 256x32 tiles, split rings, nt-load(unshifted planes) nt-store", 2},
+    {256, 16, 1, 0, "two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
+    {256, 32, 1, 0, "two steps per launch, 256x32 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
 };
 
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
@@ -1719,13 +1722,13 @@ hipError_t go9pf(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
 }
 
 template <int ST, int CO, int BX, int H, int RS, int NT = 0, int WPE = 0>
-hipError_t go9t2(const void *src, void *dst, StepArgs a, hipStream_t s)
+hipError_t go9t2(const void *src, void *dst, StepArgs a, int swz, hipStream_t s)
 {
     using T = typename Form<ST>::T;
     const int tiles_x = (a.one.nx + BX - 1) / BX;
     const int tiles_y = (a.one.ny + H - 1) / H;
     a.tiles_x = tiles_x;
-    a.xcd_swizzle = 0;
+    a.xcd_swizzle = swz;
     const dim3 grid = tiles_y <= kMaxGridY ? dim3(tiles_x, tiles_y) : dim3(tiles_x * tiles_y);
     hipLaunchKernelGGL((k_d2q9_t2<ST, CO, BX, H, RS, NT, WPE>), grid, dim3(BX), t2_lds_bytes<T>(BX, H, RS), s,
                        (const T *)src, (T *)dst, a);
@@ -1749,8 +1752,9 @@ hipError_t prep9t2()
 template <int ST, int CO>
 hipError_t dispatch9t2(int v, bool prep, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
-#define LBM_T2(BX, H, RS, NT, WPE) \
-    return prep ? prep9t2<ST, CO, BX, H, RS, NT, WPE>() : go9t2<ST, CO, BX, H, RS, NT, WPE>(src, dst, a, s)
+#define LBM_T2(BX, H, RS, NT, WPE)                                                            \
+    return prep ? prep9t2<ST, CO, BX, H, RS, NT, WPE>()                                       \
+                : go9t2<ST, CO, BX, H, RS, NT, WPE>(src, dst, a, kShapes[v].swz, s)
     switch (v) {
     case 26: LBM_T2(256, 32, 4, 6, 0);
     case 27: LBM_T2(256, 16, 4, 6, 0);
@@ -1764,6 +1768,9 @@ hipError_t dispatch9t2(int v, bool prep, const void *src, void *dst, const StepA
     case 35: LBM_T2(256, 24, 3, 6, 5);
     case 36: LBM_T2(512, 16, 4, 6, 0);
     case 37: LBM_T2(256, 16, 0, 6, 0);
+    case 38: LBM_T2(256, 32, 0, 6, 0);
+    case 39: LBM_T2(256, 16, 0, 6, 4);
+    case 40: LBM_T2(256, 32, 0, 6, 4);
     default: return hipErrorInvalidValue;
     }
 #undef LBM_T2
