@@ -164,14 +164,16 @@ int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
 
 /* Time the candidate launch shapes of the fused kernel on this context's own
  * buffers (the state is left unchanged) and keep the fastest: every shape
- * is timed, then the five fastest again with longer trials taken in turn.
+ * is timed, then the five fastest again with longer trials taken in turn
+ * over six rounds.
  * Candidates produce bitwise identical results.  If cache_path is not NULL
  * the choice is read from / appended to that text file, keyed by a hash of
  * the kernel sources, device, lattice, precision, collision, boundary and
  * size.  *chosen (may be NULL) receives the index of the chosen shape.
  * A single lattice whose planes hold at least 1 MiB also has its plane pad
- * tuned (see lbm_set_plane_pad) with the chosen shape; the cache line then
- * carries the pad too.  Synchronises.  For a batch, shapes with another tile
+ * tuned (see lbm_set_plane_pad) together with the two fastest shapes, and
+ * the fastest (shape, pad) pair is kept; the cache line then carries the
+ * pad too.  Synchronises.  For a batch, shapes with another tile
  * size rebuild the tile tables (a device allocation). */
 int lbm_autotune(lbm_ctx_t *ctx, const char *cache_path, int32_t *chosen);
 

@@ -1674,6 +1674,8 @@ constexpr Shape kShapes[] = {
     {256, 32, 1, 0, "two steps per launch, 256x32 tiles, split rings, nt-load(unshifted planes) nt-store", 2},
     {256, 16, 1, 0, "two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
     {256, 32, 1, 0, "two steps per launch, 256x32 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
+    {512, 32, 1, 0, "two steps per launch, 512x32 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
+    {1024, 32, 1, 0, "two steps per launch, 1024x32 tiles, split rings, nt-load(unshifted planes) nt-store waves>=4", 2},
 };
 
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
@@ -1771,6 +1773,8 @@ hipError_t dispatch9t2(int v, bool prep, const void *src, void *dst, const StepA
     case 38: LBM_T2(256, 32, 0, 6, 0);
     case 39: LBM_T2(256, 16, 0, 6, 4);
     case 40: LBM_T2(256, 32, 0, 6, 4);
+    case 41: LBM_T2(512, 32, 0, 6, 4);
+    case 42: LBM_T2(1024, 32, 0, 6, 4);
     default: return hipErrorInvalidValue;
     }
 #undef LBM_T2

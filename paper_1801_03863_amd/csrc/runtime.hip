@@ -826,7 +826,7 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
     // in turn so that clock drift affects them alike.
     const int nc = (int)std::min<size_t>(5, t1.size());
     std::vector<float> t2(nc, 1e30f);
-    for (int round = 0; round < 4; ++round) {
+    for (int round = 0; round < 6; ++round) {
         for (int k = 0; k < nc; ++k) {
             float ms = 0.0f;
             int rc = time_shape(t1[k].second, 4 * reps, 1, ms);
@@ -834,32 +834,39 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
             t2[k] = std::min(t2[k], ms);
         }
     }
-    int best_v = t1[0].second;
-    float best = t2[0];
-    for (int k = 1; k < nc; ++k) {
-        if (t2[k] < best) {
-            best = t2[k];
-            best_v = t1[k].second;
-        }
-    }
+    std::vector<std::pair<float, int>> ranked;
+    for (int k = 0; k < nc; ++k) ranked.emplace_back(t2[k], t1[k].second);
+    std::sort(ranked.begin(), ranked.end());
+    int best_v = ranked[0].second;
     // Stage 3, single lattices with large planes: the plane pad, timed with
-    // the chosen shape in turn over the candidates (the state moves with it).
+    // the two fastest shapes (a shape's rank can depend on the pad) in turn
+    // over the candidates (the state moves with it); the fastest pair wins.
     if (c->pad >= 0) {
         constexpr int np = (int)(sizeof(kPadCandidates) / sizeof(kPadCandidates[0]));
-        float tp[np];
-        for (int k = 0; k < np; ++k) tp[k] = 1e30f;
+        const int ns = (int)std::min<size_t>(2, ranked.size());
+        float tp[2][np];
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < np; ++k) tp[j][k] = 1e30f;
         for (int round = 0; round < 3; ++round) {
             for (int k = 0; k < np; ++k) {
                 int rc = set_pad(c, kPadCandidates[k]);
-                float ms = 0.0f;
-                if (rc == LBM_OK) rc = time_shape(best_v, 4 * reps, 1, ms);
                 if (rc) return rc;
-                tp[k] = std::min(tp[k], ms);
+                for (int j = 0; j < ns; ++j) {
+                    float ms = 0.0f;
+                    rc = time_shape(ranked[j].second, 4 * reps, 1, ms);
+                    if (rc) return rc;
+                    tp[j][k] = std::min(tp[j][k], ms);
+                }
             }
         }
-        int kb = 0;
-        for (int k = 1; k < np; ++k)
-            if (tp[k] < tp[kb]) kb = k;
+        int jb = 0, kb = 0;
+        for (int j = 0; j < ns; ++j)
+            for (int k = 0; k < np; ++k)
+                if (tp[j][k] < tp[jb][kb]) {
+                    jb = j;
+                    kb = k;
+                }
+        best_v = ranked[jb].second;
         int rc = set_pad(c, kPadCandidates[kb]);
         if (rc) return rc;
     }
