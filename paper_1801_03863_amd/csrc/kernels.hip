@@ -1888,13 +1888,19 @@ hipError_t dispatch9bt2(int v, bool prep, const void *src, void *dst, const Step
     }
 #undef LBM_BT2W
 #define LBM_BT2(BX, H, RS, NT) return prep ? prep9bt2<ST, CO, BX, H, RS, NT>() : go9bt2<ST, CO, BX, H, RS, NT>(src, dst, a, s)
+#define LBM_BT2B(BX, H, RS, NT, WPE) \
+    return prep ? prep9bt2<ST, CO, BX, H, RS, NT, WPE>() : go9bt2<ST, CO, BX, H, RS, NT, WPE>(src, dst, a, s)
     switch (v) {
     case 9: LBM_BT2(64, 16, 3, 6);
     case 10: LBM_BT2(64, 16, 0, 6);
     case 11: LBM_BT2(256, 16, 4, 6);
+    case 14: LBM_BT2(256, 16, 3, 6);
+    case 15: LBM_BT2(256, 16, 0, 6);
+    case 16: LBM_BT2B(256, 16, 3, 6, 5);
     default: return hipErrorInvalidValue;
     }
 #undef LBM_BT2
+#undef LBM_BT2B
 }
 
 template <int ST, int CO>
@@ -2058,7 +2064,10 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {64, 1, "batch two steps per launch, 64x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2, 16},
                                 {256, 1, "batch two steps per launch, 256x16 tiles, nt-load(unshifted planes) nt-store", 2, 16},
                                 {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
-                                {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), split rings, nt-load(unshifted planes) nt-store", 2, 16}};
+                                {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), split rings, nt-load(unshifted planes) nt-store", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2, 16}};
 // Single-step batch shapes (every collision rule); the rest of kShapesB9 are
 // two-step shapes of MinxEnt4.
 constexpr int kNumB9One = 9;
