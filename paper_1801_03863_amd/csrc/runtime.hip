@@ -566,7 +566,8 @@ std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices] = {};
 
 // Device address of `scratch` on the current device, looked up once per
-// device with that device current.
+// device with that device current (after checking that the device is a
+// gfx950, so later calls on it skip the property query).
 int scratch_address(void **out)
 {
     int dev = 0;
@@ -574,6 +575,9 @@ int scratch_address(void **out)
     if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ENODEV, "device index out of range");
     std::lock_guard<std::mutex> lock(g_scratch_mu);
     if (!g_scratch_ptr[dev]) {
+        std::string arch;
+        int rc = check_device(&arch);
+        if (rc) return rc;
         void *ptr = nullptr;
         hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
         if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
@@ -1012,9 +1016,6 @@ int lbm_run_noalloc(const lbm_params_t *p, const double *rho, const double *ux, 
                       need, (size_t)LBM_NOALLOC_SCRATCH_BYTES);
         return LBM_EINVAL;
     }
-    std::string arch;
-    rc = check_device(&arch);
-    if (rc) return rc;
     void *base = nullptr;
     rc = scratch_address(&base);
     if (rc) return rc;
