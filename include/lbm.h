@@ -164,7 +164,7 @@ int lbm_set_graph_chunk(lbm_ctx_t *ctx, int32_t chunk);
 
 /* Time the candidate launch shapes of the fused kernel on this context's own
  * buffers (the state is left unchanged) and keep the fastest: every shape
- * is timed, then the five fastest again with longer trials taken in turn
+ * is timed, then the eight fastest again with longer trials taken in turn
  * over six rounds.
  * Candidates produce bitwise identical results.  If cache_path is not NULL
  * the choice is read from / appended to that text file, keyed by a hash of

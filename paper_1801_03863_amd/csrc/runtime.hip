@@ -826,9 +826,9 @@ int lbm_autotune(lbm_ctx_t *c, const char *cache_path, int32_t *chosen)
         t1.emplace_back(ms, v);
     }
     std::sort(t1.begin(), t1.end());
-    // Stage 2: the five fastest again with four times longer trials, taken
+    // Stage 2: the eight fastest again with four times longer trials, taken
     // in turn so that clock drift affects them alike.
-    const int nc = (int)std::min<size_t>(5, t1.size());
+    const int nc = (int)std::min<size_t>(8, t1.size());
     std::vector<float> t2(nc, 1e30f);
     for (int round = 0; round < 6; ++round) {
         for (int k = 0; k < nc; ++k) {
