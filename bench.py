@@ -485,11 +485,57 @@ def oracle_cavity_256_stored():
                       "on the build host)" % (n, n, steps)}
 
 
+def oracle_batch_subsets(cavities=3, tubes=16):
+    """Seeded subsets of the two batches run whole in the oracle (one core):
+    the smallest cavities of the 512-cavity batch for their 5000 steps and the
+    shortest tubes of the 4096-tube batch for their 1000 steps; the rate is
+    extrapolated to the whole batch by lattice updates."""
+    from oracle import oracle as O
+    from paper_1801_03863_amd import inputs as I
+    out = {}
+    insts = I.cavity_batch(count=512)
+    order = sorted(range(len(insts)), key=lambda i: insts[i][0])[:cavities]
+    lu = secs = 0.0
+    for i in order:
+        m, tau, re = insts[i]
+        r, u, v = I.cavity_fields(m, 1.0, 1804 * 1000 + i)
+        t0 = time.perf_counter()
+        O.run(O.D2Q9, O.MINXENT4, O.BC_CAVITY, m, m, tau, r, u, v, steps=5000, u_lid=0.1)
+        secs += time.perf_counter() - t0
+        lu += m * m * 5000
+    total = sum(m * m for m, tau, re in insts) * 5000
+    rate = lu / secs / 1e6
+    out["cavities_512_fp64"] = {
+        "value": round(rate, 3), "unit": "MLUPS", "cores": 1, "seconds": round(secs, 2),
+        "extrapolated_whole_batch_hours": round(total / (rate * 1e6) / 3600, 2),
+        "sample": "the %d smallest cavities of the 512-cavity batch (sides %s), 5000 steps each, whole; "
+                  "extrapolated to the batch by lattice updates" % (cavities, [insts[i][0] for i in order])}
+    tb = I.tube_batch(count=4096)
+    order = sorted(range(len(tb)), key=lambda i: tb[i][0])[:tubes]
+    lu = secs = 0.0
+    for i in order:
+        m, rl, rr, tau = tb[i]
+        r, u = I.tube_fields(m, rl, rr)[:2]
+        t0 = time.perf_counter()
+        O.run(O.D1Q3, O.SRT, O.BC_TUBE, m, 1, tau, r, u, steps=1000)
+        secs += time.perf_counter() - t0
+        lu += m * 1000
+    total = sum(t[0] for t in tb) * 1000
+    rate = lu / secs / 1e6
+    out["tubes_4096_fp64"] = {
+        "value": round(rate, 3), "unit": "MLUPS", "cores": 1, "seconds": round(secs, 2),
+        "extrapolated_whole_batch_hours": round(total / (rate * 1e6) / 3600, 3),
+        "sample": "the %d shortest tubes of the 4096-tube batch (%d-%d nodes), 1000 steps each, whole; "
+                  "extrapolated to the batch by lattice updates" % (tubes, tb[order[0]][0], tb[order[-1]][0])}
+    return out
+
+
 def cpu_baseline(n, tau, u_lid, seed, rows=512, steps=8, all_cores=True):
     """The FP64 oracle, single-threaded, on rows [0, rows) of the same cavity
     (bottom wall included) for `steps` steps; init and read-back cost removed
     by subtracting a zero-step run of the same window.  Beside it: the
-    all-cores figure, the whole 800-node tube, and the stored 256^2 time."""
+    all-cores figure, the whole 800-node tube, the stored 256^2 time and
+    whole-length subsets of the two batches."""
     from oracle import oracle as O
     from paper_1801_03863_amd import inputs as I
     r, u, v = I.cavity_fields_window(n, 0, 0, n, rows, 1.0, seed)
@@ -509,6 +555,7 @@ def cpu_baseline(n, tau, u_lid, seed, rows=512, steps=8, all_cores=True):
         out["all_cores"] = oracle_all_cores(n, tau, u_lid, seed, steps)
     out["tube800_full"] = oracle_tube_800()
     out["cavity256_20000_stored"] = oracle_cavity_256_stored()
+    out.update(oracle_batch_subsets())
     return out
 
 
