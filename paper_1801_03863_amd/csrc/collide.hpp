@@ -443,36 +443,35 @@ __device__ __forceinline__ bool collide_minxent(C (&f)[9], C omega, C omega2, bo
     bool ok;
     C p1, F, R;
     if constexpr (sizeof(C) == 8 || SHARED_RCP) {
-        // Montgomery's simultaneous inversion over the order
-        // 5 6 7 8 1 2 3 4 0: the prefix product after four factors is F, and
-        // the running reciprocal after the first back-substitution step is
-        // 1/(F f1 f2 f3 f4), so R = F times it.
+        // Simultaneous inversion (Montgomery's trick) over a product tree:
+        // pairs 56, 78, 12, 34, quads F = f5 f6 f7 f8 and G = f1 f2 f3 f4,
+        // and the product of all nine; one reciprocal of that product is
+        // taken back down the tree.  1/G is R itself.  The tree keeps fewer
+        // partial products live than a running chain and its dependent
+        // chains are three products deep instead of eight.
         p1 = f0[5] * f0[6];
-        const C p2 = p1 * f0[7];
-        F = p2 * f0[8];
-        const C p4 = F * f0[1];
-        const C p5 = p4 * f0[2];
-        const C p6 = p5 * f0[3];
-        const C p7 = p6 * f0[4];
-        const C p8 = p7 * f0[0];
-        C q = lean ? rcp1(p8) : rcp(p8);
-        r[0] = q * p7;
-        q = q * f0[0];
-        R = F * q;
-        r[4] = q * p6;
-        q = q * f0[4];
-        r[3] = q * p5;
-        q = q * f0[3];
-        r[2] = q * p4;
-        q = q * f0[2];
-        r[1] = q * F;
-        q = q * f0[1];
-        r[8] = q * p2;
-        q = q * f0[8];
-        r[7] = q * p1;
-        q = q * f0[7];
-        r[6] = q * f0[5];
-        r[5] = q * f0[6];
+        const C p78 = f0[7] * f0[8];
+        const C p12 = f0[1] * f0[2];
+        const C p34 = f0[3] * f0[4];
+        F = p1 * p78;
+        const C G = p12 * p34;
+        const C FG = F * G;
+        const C p8 = FG * f0[0];
+        const C q = lean ? rcp1(p8) : rcp(p8);
+        r[0] = q * FG;
+        const C qa = q * f0[0];  // 1/(F G)
+        const C iF = qa * G;
+        R = qa * F;
+        const C i56 = iF * p78, i78 = iF * p1;
+        const C i12 = R * p34, i34 = R * p12;
+        r[5] = i56 * f0[6];
+        r[6] = i56 * f0[5];
+        r[7] = i78 * f0[8];
+        r[8] = i78 * f0[7];
+        r[1] = i12 * f0[2];
+        r[2] = i12 * f0[1];
+        r[3] = i34 * f0[4];
+        r[4] = i34 * f0[3];
         if constexpr (sizeof(C) == 8)
             ok = !any_sign9(f0) && p8 > 2.2250738585072014e-308 && p8 < C(__builtin_huge_val());
         else

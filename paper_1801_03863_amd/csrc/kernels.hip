@@ -219,23 +219,22 @@ __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s
     for (int q = 0; q < 9; ++q) f[q] = load<ST>(&r[q], ref[q], iscale);
 }
 
-// Write the nine post-collision populations of node (x, y) of a row that is
-// uniform across the wave.  The row base is read from the first lane so that
-// it lives in scalar registers, and each store takes the scalar-base +
-// 32-bit vector-offset form of a global store.
+// Write the nine populations of node (x, y), already in their storage form,
+// of a row that is uniform across the wave.  The row base is read from the
+// first lane so that it lives in scalar registers, and each store takes the
+// scalar-base + 32-bit vector-offset form of a global store.
 template <int ST, bool NT = false>
-__device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
-                                         const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
-                                         float scale)
+__device__ __forceinline__ void push9_xy_st(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
+                                            const typename Form<ST>::T (&v)[9])
 {
     using T = typename Form<ST>::T;
     using GT = __attribute__((address_space(1))) T;
-    const uint64_t v = (uint64_t)d + (uint64_t)((int64_t)y * nx * (int64_t)sizeof(T));
+    const uint64_t a = (uint64_t)d + (uint64_t)((int64_t)y * nx * (int64_t)sizeof(T));
     // readfirstlane returns a signed int: each half goes through uint32_t so
     // that widening zero-extends it.
-    const uint32_t vhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    const uint32_t vlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint64_t b = ((uint64_t)vhi << 32) | (uint64_t)vlo;
+    const uint32_t ahi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    const uint32_t alo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint64_t b = ((uint64_t)ahi << 32) | (uint64_t)alo;
     const uint64_t PB = (uint64_t)P * sizeof(T);
     // The empty asm statements keep the lane offset and each plane base
     // opaque, so the compiler can neither share a widened offset with the
@@ -247,12 +246,21 @@ __device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, i
         uint64_t bq = b + q * PB;
         asm volatile("" : "+s"(bq));
         GT *p = (GT *)(bq + (uint64_t)o);
-        T t;
-        if constexpr (ST == ST_F16DEV) t = enc16(f[q], ref[q], scale);
-        else t = T(f[q]);
-        if constexpr (NT) __builtin_nontemporal_store(t, p);
-        else *p = t;
+        if constexpr (NT) __builtin_nontemporal_store(v[q], p);
+        else *p = v[q];
     }
+}
+
+// The same from populations in compute precision.
+template <int ST, bool NT = false>
+__device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
+                                         const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
+                                         float scale)
+{
+    typename Form<ST>::T v[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[q] = to_storage<ST>(f[q], ref[q], scale);
+    push9_xy_st<ST, NT>(d, P, x, y, nx, v);
 }
 
 // Address of a block-uniform pointer, read from the first lane so that it
@@ -289,6 +297,37 @@ __device__ __forceinline__ void pull9_inst(uint64_t s, int64_t P, uint32_t rc, u
         uint32_t oq = o[q];
         asm volatile("" : "+v"(oq));
         GT *p = (GT *)(bq + (uint64_t)oq);
+        if (nt[q]) r[q] = __builtin_nontemporal_load(p);
+        else r[q] = *p;
+    }
+}
+
+// Pull of a row that is uniform across the block (the two-step kernel's
+// window rows): rows y (own), ym (below), yp (above), columns as byte
+// offsets cc, cm, cp.  Each row and plane base lives in scalar registers and
+// each load takes the scalar-base + 32-bit vector-offset form, so no lane
+// forms a 64-bit address.  NL as for pull9_cols.
+template <int ST, int NL>
+__device__ __forceinline__ void pull9_row_u(const typename Form<ST>::T *__restrict__ s, int64_t P, int y, int ym,
+                                            int yp, int nx, uint32_t cc, uint32_t cm, uint32_t cp,
+                                            typename Form<ST>::T (&r)[9])
+{
+    using T = typename Form<ST>::T;
+    using GT = const __attribute__((address_space(1))) T;
+    constexpr bool A = NL == 1, U = NL != 0;
+    constexpr bool nt[9] = {U, A, U, A, U, A, A, A, A};
+    constexpr int row[9] = {0, 0, 1, 0, 2, 1, 1, 2, 2};  // own, below, above
+    constexpr int col[9] = {0, 1, 0, 2, 0, 1, 2, 2, 1};  // own, left, right
+    const uint64_t s0 = uniform_addr(s);
+    const uint64_t RB = (uint64_t)nx * sizeof(T), PB = (uint64_t)P * sizeof(T);
+    const uint64_t rb[3] = {s0 + (uint64_t)y * RB, s0 + (uint64_t)ym * RB, s0 + (uint64_t)yp * RB};
+    uint32_t co[3] = {cc, cm, cp};
+    asm volatile("" : "+v"(co[0]), "+v"(co[1]), "+v"(co[2]));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        uint64_t bq = rb[row[q]] + q * PB;
+        asm volatile("" : "+s"(bq));
+        GT *p = (GT *)(bq + (uint64_t)co[col[q]]);
         if (nt[q]) r[q] = __builtin_nontemporal_load(p);
         else r[q] = *p;
     }
@@ -853,7 +892,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         const int gy = row_of(j);
         if (cavity && gy == ny - 1) return;  // the lid row loads nothing
         const Nb n = neighbours(0, gy, 1, ny, a.bc);  // rows only
-        pull9_cols<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, r);
+        pull9_row_u<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, r);
     };
     T raw[9];
     pull_row(0, raw);
@@ -874,6 +913,9 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
 
     int bad1 = kNoNode, bad2 = kNoNode;
     int guarded = 0;
+    T lid_st[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lid_st[q] = to_storage<ST>(C(in.lid[q]), ref[q], a.fp16_scale);
     sync();  // halo array complete
 
     // Iteration j: first step of window row j from raw (loaded in the
@@ -889,23 +931,29 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         T v0 = T(0), v2 = T(0), v4 = T(0);  // RS = 0: the unshifted planes of row j
         {
             const int gy = row_of(j);
-            C f[9];
+            // The row's populations in storage form, converted once for the
+            // ring and the direct write: the lid row's are the lid
+            // equilibrium's (uniform), any other row's its first step's.
+            T sv[9];
             int fl = 0;
             if (cavity && gy == ny - 1) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) f[q] = C(in.lid[q]);
+                for (int q = 0; q < 9; ++q) sv[q] = lid_st[q];
             } else {
+                C f[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
                 fl = node9_row<ST, CO>(f, xs, gy, nx, ny, a.bc, in);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) sv[q] = to_storage<ST>(f[q], ref[q], a.fp16_scale);
             }
             const bool own = j >= 1 && j <= hn && xin;
             if (own && (fl & 1)) bad1 = min(bad1, gy * nx + x);
             guarded += __popcll(__ballot(own && (fl & 2)));
-            if (kdo == 1 && own) push9_xy<ST, (NT & 2) != 0>(dst, P, x, gy, nx, f, ref, a.fp16_scale);
+            if (kdo == 1 && own) push9_xy_st<ST, (NT & 2) != 0>(dst, P, x, gy, nx, sv);
             if constexpr (RS != 0) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) store<ST>(plane(q, j) + t + 1, f[q], ref[q], a.fp16_scale);
+                for (int q = 0; q < 9; ++q) plane(q, j)[t + 1] = sv[q];
                 if (t < 18) {
                     const int side = t >= 9, q = t - 9 * side;
                     plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
@@ -914,11 +962,11 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const int q = kShifted[k];
-                    store<ST>(plane(q, j) + t + 1, f[q], ref[q], a.fp16_scale);
+                    plane(q, j)[t + 1] = sv[q];
                 }
-                v0 = to_storage<ST>(f[0], ref[0], a.fp16_scale);
-                v2 = to_storage<ST>(f[2], ref[2], a.fp16_scale);
-                v4 = to_storage<ST>(f[4], ref[4], a.fp16_scale);
+                v0 = sv[0];
+                v2 = sv[2];
+                v4 = sv[4];
                 if (t < 12) {
                     const int side = t >= 6, q = kShifted[t - 6 * side];
                     plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
