@@ -716,8 +716,9 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // --------------------------------------------------------------------------
 // D2Q9, one lattice, two steps per launch (temporal blocking).
 //
-// A block of BX threads owns an output tile of BX columns and H rows.  It
-// walks a window that is one node wider on every side: window column i is
+// A block of BX threads owns an output tile of BX columns and H rows (in a
+// batch, of the instance's tile width tw <= BX, below).  It walks a window
+// that is one node wider on every side: window column i is
 // lattice column x0 - 1 + i and window row j is lattice row y0 - 1 + j, each
 // mapped into the lattice by the neighbour rule (wrapped on periodic axes,
 // clamped otherwise).  The first step computes every window node exactly as
@@ -738,9 +739,10 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // just computed, plane 0 of the row before, plane 2 of the row before that);
 // planes 7 and 8 are read in the iteration that writes them (two slots),
 // 1 and 3 one iteration later (three), 5 and 6 two iterations later (four).
-// That is 18 plane-rows of LDS instead of 36, with one barrier per row.  The two halo columns of every window row are computed
-// first, by the first 2 (H + 2) threads, into their own LDS array, and copied
-// into the ring as each row is written.  Each first-step row's loads are
+// That is 18 plane-rows of LDS instead of 36, with one barrier per row.  The
+// two halo columns of every window row are computed first, by the first
+// 2 (H + 2) threads, into their own LDS array, and copied into the ring as
+// each row is written.  Each first-step row's loads are
 // issued one iteration ahead, before the barrier, and complete during the
 // second step of the row before.
 // Only nodes inside the tile report status (first step at a.step, second at
@@ -860,11 +862,25 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
     const bool yw = a.bc == BC_PERIODIC || a.bc == BC_TUBE;
     const bool cavity = a.bc == BC_CAVITY;
     const int t = WT > 0 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-    const int x0 = tx * BX, y0 = ty * H;
+    // Tile width: BX, or in a batch the instance's columns spread evenly over
+    // its tiles_x tiles, rounded up to whole waves (an instance 300 wide
+    // takes two tiles of 192 columns instead of two of 256).  The waves of a
+    // block that hold no needed column, beyond the tile's width or beyond the
+    // column just past the instance's edge, skip the arithmetic and keep
+    // every barrier.
+    constexpr bool BAL = BATCH && WT == 0;
+    int tw = BX;
+    if constexpr (BAL) tw = min(BX, ((nx + tiles_x - 1) / tiles_x + 63) & ~63);
+    const int x0 = tx * tw, y0 = ty * H;
     const int hn = min(H, ny - y0);  // output rows of this tile (block-uniform)
     const int x = x0 + t;
-    const bool xin = x < nx;
+    const bool xin = (!BAL || t < tw) && x < nx;
     const int xs = t2_map(x, nx, xw);  // lattice column of this thread's window column
+    bool wave_on = true;
+    if constexpr (BAL) {
+        const int t0 = __builtin_amdgcn_readfirstlane(t & ~63);
+        wave_on = t0 < tw && t0 <= nx - x0;
+    }
 
     // Steps this launch takes here (block-uniform): two; one for an odd step
     // count's last step, or for a batch instance whose step limit falls
@@ -895,12 +911,12 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         pull9_row_u<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, r);
     };
     T raw[9];
-    pull_row(0, raw);
+    if (wave_on) pull_row(0, raw);
 
-    // Halo columns (x0 - 1 and x0 + BX) of every window row, first step.
+    // Halo columns (x0 - 1 and x0 + tw) of every window row, first step.
     for (int k = t; k < 2 * (hn + 2); k += BX) {
         const int side = k & 1, j = k >> 1;
-        const int gx = t2_map(side ? x0 + BX : x0 - 1, nx, xw);
+        const int gx = t2_map(side ? x0 + tw : x0 - 1, nx, xw);
         const int gy = row_of(j);
         C f[9];
         const Nb n = neighbours(gx, gy, nx, ny, a.bc);
@@ -913,6 +929,20 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
 
     int bad1 = kNoNode, bad2 = kNoNode;
     int guarded = 0;
+    if constexpr (BAL) {
+        if (!wave_on) {
+            // A wave without a needed column takes only the block's barriers,
+            // as many and in the order the row loop below takes them.
+            sync();  // halo array complete
+            for (int j = 0; j < nj; ++j) {
+                if constexpr (RS == 3) {
+                    if (j > 0) sync();
+                }
+                sync();
+            }
+            return;
+        }
+    }
     T lid_st[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) lid_st[q] = to_storage<ST>(C(in.lid[q]), ref[q], a.fp16_scale);
@@ -937,6 +967,9 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
             T sv[9];
             int fl = 0;
             if (cavity && gy == ny - 1) {
+                // (An empty statement gives this path a block of its own, so
+                // that the copies below are not hoisted onto every row.)
+                asm volatile("");
 #pragma unroll
                 for (int q = 0; q < 9; ++q) sv[q] = lid_st[q];
             } else {
@@ -956,7 +989,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
                 for (int q = 0; q < 9; ++q) plane(q, j)[t + 1] = sv[q];
                 if (t < 18) {
                     const int side = t >= 9, q = t - 9 * side;
-                    plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                    plane(q, j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 9 + q];
                 }
             } else {
 #pragma unroll
@@ -969,7 +1002,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
                 v4 = sv[4];
                 if (t < 12) {
                     const int side = t >= 6, q = kShifted[t - 6 * side];
-                    plane(q, j)[side ? W - 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                    plane(q, j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 9 + q];
                 }
             }
         }
