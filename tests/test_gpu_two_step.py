@@ -164,8 +164,10 @@ def _run_batch(b, params, r, u, v, variant, steps, graph=0):
 @pytest.mark.parametrize("precision", ["fp32_newton64", "fp64", "fp16dev"])
 def test_batch_two_step_shapes_bitwise(precision):
     # widths below, equal to and ragged against 64, 128 and 256; a tall
-    # instance; the smallest lattice
-    sizes = [(3, 3), (64, 17), (65, 40), (130, 33), (300, 21), (7, 150), (257, 64)]
+    # instance; the smallest lattice; 320 wide, whose second tile of 192
+    # columns (balanced tile widths) ends its instance 128 columns in, so the
+    # column just past the edge is the first lane of a wave
+    sizes = [(3, 3), (64, 17), (65, 40), (130, 33), (300, 21), (7, 150), (257, 64), (320, 9)]
     b = B()
     params, r, u, v = _batch(b, sizes, precision)
     for steps, graph in ((10, 0), (9, 0), (11, 4)):

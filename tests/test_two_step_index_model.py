@@ -90,18 +90,27 @@ def ring_slot(rs, q, j):
     return ("C", j % 4, q - 5)
 
 
-def two_steps(f, nx, ny, bc, bx, h, rs):
+def two_steps(f, nx, ny, bc, bx, h, rs, wave=None):
+    """wave: None for tiles of bx columns; else the batch kernel's balanced
+    tiles, wave lanes to a wave: the instance's columns spread evenly over
+    its ceil(nx / bx) tiles, rounded up to whole waves, with the waves that
+    hold no needed column left out of both steps."""
     xw, yw = bc == "periodic", bc in ("periodic", "tube")
     w = bx + 2
     out = np.full_like(f, np.nan)
+    tiles_x = (nx + bx - 1) // bx
+    tw = bx if wave is None else min(bx, -(-(-(-nx // tiles_x)) // wave) * wave)
     for ty in range((ny + h - 1) // h):
-        for tx in range((nx + bx - 1) // bx):
-            x0, y0 = tx * bx, ty * h
+        for tx in range(tiles_x):
+            x0, y0 = tx * tw, ty * h
             hn = min(h, ny - y0)
+            # lanes of the waves that take part (all of them for bx-wide tiles)
+            lanes = [t for t in range(bx) if wave is None or
+                     ((t // wave) * wave < tw and (t // wave) * wave <= nx - x0)]
             halo = np.full((h + 2, 2, 9), np.nan, np.float32)
             for k in range(2 * (hn + 2)):
                 side, j = k & 1, k >> 1
-                gx = window_map(x0 + bx if side else x0 - 1, nx, xw)
+                gx = window_map(x0 + tw if side else x0 - 1, nx, xw)
                 gy = window_map(y0 - 1 + j, ny, yw)
                 halo[j, side] = collide(pull(f, gx, gy, nx, ny, bc), role(gx, gy, nx, ny, bc))
             rings = {"full": np.full((max(rs, 1), 9, w), np.nan, np.float32),
@@ -129,22 +138,24 @@ def two_steps(f, nx, ny, bc, bx, h, rs):
             u2a, u2b = u0.copy(), u0.copy()
             for j in range(hn + 2):
                 gy = window_map(y0 - 1 + j, ny, yw)
-                v = np.stack([collide(pull(f, window_map(x0 + t, nx, xw), gy, nx, ny, bc),
-                                      role(window_map(x0 + t, nx, xw), gy, nx, ny, bc)) for t in range(bx)], axis=1)
+                v = np.full((9, bx), np.nan, np.float32)
+                for t in lanes:
+                    v[:, t] = collide(pull(f, window_map(x0 + t, nx, xw), gy, nx, ny, bc),
+                                      role(window_map(x0 + t, nx, xw), gy, nx, ny, bc))
                 written = range(9) if rs else SHIFTED
                 for q in written:
                     row = write(q, j)
                     row[1:bx + 1] = v[q]
                     row[0] = halo[j, 0, q]
-                    row[w - 1] = halo[j, 1, q]
+                    row[tw + 1] = halo[j, 1, q]
                 s0, s2 = u0, u2b
                 u0, u2b, u2a = v[0].copy(), u2a, v[2].copy()
                 if j < 2:
                     continue
                 y = y0 + j - 2
-                for t in range(bx):
+                for t in lanes:
                     x = x0 + t
-                    if x >= nx:
+                    if t >= tw or x >= nx:
                         continue
                     if rs:
                         p0, p2, p4 = read(0, j - 1, j)[t + 1], read(2, j - 2, j)[t + 1], read(4, j, j)[t + 1]
@@ -168,6 +179,24 @@ def test_two_step_indexing_equals_two_single_steps(rs, bc):
         f = rng.random((9, ny, nx)).astype(np.float32)
         assert np.array_equal(two_steps(f, nx, ny, bc, bx, h, rs), one_step(one_step(f, nx, ny, bc), nx, ny, bc)), \
             (nx, ny, bx, h)
+
+
+@pytest.mark.parametrize("rs", [3, 0])
+@pytest.mark.parametrize("bc", ["cavity", "periodic"])
+def test_balanced_batch_tiles_equal_two_single_steps(rs, bc):
+    # Widths against 16-lane tiles of 4-lane waves (a 256-thread block of
+    # 64-lane waves scaled down): narrower than a tile, a whole number of
+    # waves, one column past a tile, two uneven tiles; every needed column is
+    # computed by a wave that takes part, and no lane reads a ring entry that
+    # a skipped wave would have written.
+    rng = np.random.default_rng(8)
+    # (20 and 28: the last tile's one-past-the-edge column is the first lane
+    # of a wave, which must still take part)
+    for nx, ny in [(3, 5), (4, 6), (5, 4), (8, 5), (13, 3), (16, 4), (17, 5), (19, 4), (20, 4), (28, 3), (30, 3),
+                   (33, 4)]:
+        f = rng.random((9, ny, nx)).astype(np.float32)
+        assert np.array_equal(two_steps(f, nx, ny, bc, 16, 2, rs, wave=4),
+                              one_step(one_step(f, nx, ny, bc), nx, ny, bc)), (nx, ny)
 
 
 # --------------------------------------------------------------------------
