@@ -99,7 +99,11 @@ def two_steps(f, nx, ny, bc, bx, h, rs, wave=None):
     w = bx + 2
     out = np.full_like(f, np.nan)
     tiles_x = (nx + bx - 1) // bx
-    tw = bx if wave is None else min(bx, -(-(-(-nx // tiles_x)) // wave) * wave)
+    if wave is None:
+        tw = bx
+    else:
+        per_tile = -(-nx // tiles_x)  # ceil(nx / tiles_x)
+        tw = min(bx, -(-per_tile // wave) * wave)  # rounded up to whole waves
     for ty in range((ny + h - 1) // h):
         for tx in range(tiles_x):
             x0, y0 = tx * tw, ty * h
