@@ -60,6 +60,22 @@ def test_table_II_values(table2_run, golden, name, field, rel):
     assert abs(got / paper - 1) <= rel
 
 
+def test_table_II_lid_speed_reading(table2_run, golden):
+    # The paper names both 0.01 and 0.1 as lid speeds.  At U = 0.1 every
+    # strength falls further from the printed MinxEnt4 row than at U = 0.01
+    # (by 4-14% against 1-5%): Table II is read as the U = 0.01 run.
+    fast = E().run_cavity_steady(n=257, re=1000.0, u_lid=0.1, rho0=2.7, check_every=20000, tol=3e-6,
+                                 min_steps=200000, max_steps=1500000)
+    assert not fast["status"]["unstable"]
+    for name, field in (("main", "psi_hat"), ("lower_right", "psi_hat"), ("lower_left", "psi_hat"),
+                        ("main", "omega_hat"), ("lower_right", "omega_hat")):
+        paper = golden["table_II_minxent4"][name][field]
+        slow_err = abs(table2_run["summary"][name][field] * SCALE[name][field] / paper - 1)
+        fast_err = abs(fast["summary"][name][field] * SCALE[name][field] / paper - 1)
+        print(name, field, "U=0.01 %.4f  U=0.1 %.4f" % (slow_err, fast_err), flush=True)
+        assert fast_err > slow_err + 0.01, (name, field)
+
+
 def test_table_II_closer_to_minxent4_than_to_ef3_row(table2_run, golden):
     # The run reproduces the paper's MinxEnt4 main vortex, not its EF3 one.
     got = table2_run["summary"]["main"]["psi_hat"]
