@@ -113,8 +113,10 @@ typedef struct lbm_status {
 typedef struct lbm_ctx lbm_ctx_t;
 
 /* Bytes of device workspace a context for p needs: the two population
- * buffers (2 * b * padded nodes * bytes per stored population).  Returns
- * LBM_EINVAL for invalid parameters. */
+ * buffers (2 * b * plane stride * bytes per stored population, the plane
+ * stride as lbm_set_plane_pad states it).  Returns LBM_EINVAL for invalid
+ * parameters, among them a lattice of 2^30 nodes or more, or a D2Q9 lattice
+ * whose padded rows hold 2^31 elements or more. */
 int lbm_workspace_bytes(const lbm_params_t *p, size_t *bytes);
 
 /* Create a context and set every node to the polynomial equilibrium of the
@@ -179,7 +181,9 @@ int lbm_autotune(lbm_ctx_t *ctx, const char *cache_path, int32_t *chosen);
 
 /* Plane pad of a single lattice whose planes hold at least 1 MiB.  The b
  * population planes of a buffer follow each other at a stride of
- * round_up(nodes, 64) elements plus pad_bytes; the workspace is sized for the
+ * round_up(ny * pitch, 64) elements plus pad_bytes, where a D2Q9 row takes
+ * pitch = nx rounded up to whole 128-byte lines (its padding is never read)
+ * and a D1Q3 lattice is one row of nx; the workspace is sized for the
  * largest pad (8192 bytes), and contexts start at 2048.  A stride that is a
  * large power of two starts all planes at the same memory-channel offset, and
  * which pad avoids that best depends on the size, so the autotuner measures

@@ -8,10 +8,12 @@
 // equilibrium of the lid's density and velocity on the lid (Sec. IV.E) -- and
 // writes its nine post-collision populations to the other buffer.
 //
-// Layout: structure of arrays, one plane of nx*ny values per direction,
-// x fastest, so every plane read is a unit-stride row shifted by at most one
-// element and every write is aligned and unit-stride.  Planes follow each
-// other at a stride of the node count rounded up to 64 elements, plus, for a
+// Layout: structure of arrays, one plane per direction of ny rows of nx
+// values, x fastest, each row starting a 128-byte line (rows `pitch`
+// elements apart, nx rounded up to whole lines; the padding is never read),
+// so every plane read is a unit-stride row shifted by at most one element and
+// every write is aligned and unit-stride.  Planes follow each other at a
+// stride of ny * pitch rounded up to 64 elements, plus, for a
 // large single lattice, a tuned pad that is a multiple of 256 bytes, so every
 // plane starts 256-byte aligned.  The single-step kernels read and write
 // every population exactly once per step; they are bound by HBM bandwidth in
@@ -148,13 +150,13 @@ __device__ __forceinline__ int role9(int x, int y, int nx, int ny, int bc)
 // tile shares with its horizontal neighbour can still be found in cache.
 template <int ST, int NL = 0>
 __device__ __forceinline__ void pull9_cols(const typename Form<ST>::T *__restrict__ s, int64_t P, int y, int ym,
-                                           int yp, int nx, uint32_t cc, uint32_t cm, uint32_t cp,
+                                           int yp, int pitch, uint32_t cc, uint32_t cm, uint32_t cp,
                                            typename Form<ST>::T (&r)[9])
 {
     using T = typename Form<ST>::T;
     constexpr bool A = NL == 1, U = NL != 0;
     const int64_t PB = P * (int64_t)sizeof(T);
-    const int64_t RB = (int64_t)nx * (int64_t)sizeof(T);
+    const int64_t RB = (int64_t)pitch * (int64_t)sizeof(T);
     const char *bc_ = (const char *)s + (int64_t)y * RB;
     const char *bm_ = (const char *)s + (int64_t)ym * RB;
     const char *bp_ = (const char *)s + (int64_t)yp * RB;
@@ -197,24 +199,25 @@ __device__ __forceinline__ Cols columns(int xs, bool edge_tile, int nx, int bc, 
     return c;
 }
 
-// Pull the nine raw stored populations that stream into node (x, y).
+// Pull the nine raw stored populations that stream into node (x, y) (rows
+// `pitch` elements apart).
 template <int ST, int NL = 0>
-__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
-                                          const Nb &n, typename Form<ST>::T (&r)[9])
+__device__ __forceinline__ void pull9_raw(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y,
+                                          int pitch, const Nb &n, typename Form<ST>::T (&r)[9])
 {
     const uint32_t E = sizeof(typename Form<ST>::T);
-    pull9_cols<ST, NL>(s, P, y, n.ym, n.yp, nx, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
+    pull9_cols<ST, NL>(s, P, y, n.ym, n.yp, pitch, (uint32_t)x * E, (uint32_t)n.xm * E, (uint32_t)n.xp * E, r);
 }
 
 // Pull and widen the nine populations that stream into node (x, y) (NL as
 // for pull9_cols).
 template <int ST, int NL = 0>
-__device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y, int nx,
-                                      const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
+__device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s, int64_t P, int x, int y,
+                                      int pitch, const Nb &n, const typename Form<ST>::C (&ref)[9], float iscale,
                                       typename Form<ST>::C (&f)[9])
 {
     typename Form<ST>::T r[9];
-    pull9_raw<ST, NL>(s, P, x, y, nx, n, r);
+    pull9_raw<ST, NL>(s, P, x, y, pitch, n, r);
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = load<ST>(&r[q], ref[q], iscale);
 }
@@ -224,12 +227,12 @@ __device__ __forceinline__ void pull9(const typename Form<ST>::T *__restrict__ s
 // first lane so that it lives in scalar registers, and each store takes the
 // scalar-base + 32-bit vector-offset form of a global store.
 template <int ST, bool NT = false>
-__device__ __forceinline__ void push9_xy_st(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
-                                            const typename Form<ST>::T (&v)[9])
+__device__ __forceinline__ void push9_xy_st(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y,
+                                            int pitch, const typename Form<ST>::T (&v)[9])
 {
     using T = typename Form<ST>::T;
     using GT = __attribute__((address_space(1))) T;
-    const uint64_t a = (uint64_t)d + (uint64_t)((int64_t)y * nx * (int64_t)sizeof(T));
+    const uint64_t a = (uint64_t)d + (uint64_t)((int64_t)y * pitch * (int64_t)sizeof(T));
     // readfirstlane returns a signed int: each half goes through uint32_t so
     // that widening zero-extends it.
     const uint32_t ahi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
@@ -253,14 +256,14 @@ __device__ __forceinline__ void push9_xy_st(typename Form<ST>::T *__restrict__ d
 
 // The same from populations in compute precision.
 template <int ST, bool NT = false>
-__device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
-                                         const typename Form<ST>::C (&f)[9], const typename Form<ST>::C (&ref)[9],
-                                         float scale)
+__device__ __forceinline__ void push9_xy(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y,
+                                         int pitch, const typename Form<ST>::C (&f)[9],
+                                         const typename Form<ST>::C (&ref)[9], float scale)
 {
     typename Form<ST>::T v[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) v[q] = to_storage<ST>(f[q], ref[q], scale);
-    push9_xy_st<ST, NT>(d, P, x, y, nx, v);
+    push9_xy_st<ST, NT>(d, P, x, y, pitch, v);
 }
 
 // Address of a block-uniform pointer, read from the first lane so that it
@@ -309,7 +312,7 @@ __device__ __forceinline__ void pull9_inst(uint64_t s, int64_t P, uint32_t rc, u
 // forms a 64-bit address.  NL as for pull9_cols.
 template <int ST, int NL>
 __device__ __forceinline__ void pull9_row_u(const typename Form<ST>::T *__restrict__ s, int64_t P, int y, int ym,
-                                            int yp, int nx, uint32_t cc, uint32_t cm, uint32_t cp,
+                                            int yp, int pitch, uint32_t cc, uint32_t cm, uint32_t cp,
                                             typename Form<ST>::T (&r)[9])
 {
     using T = typename Form<ST>::T;
@@ -319,7 +322,7 @@ __device__ __forceinline__ void pull9_row_u(const typename Form<ST>::T *__restri
     constexpr int row[9] = {0, 0, 1, 0, 2, 1, 1, 2, 2};  // own, below, above
     constexpr int col[9] = {0, 1, 0, 2, 0, 1, 2, 2, 1};  // own, left, right
     const uint64_t s0 = uniform_addr(s);
-    const uint64_t RB = (uint64_t)nx * sizeof(T), PB = (uint64_t)P * sizeof(T);
+    const uint64_t RB = (uint64_t)pitch * sizeof(T), PB = (uint64_t)P * sizeof(T);
     const uint64_t rb[3] = {s0 + (uint64_t)y * RB, s0 + (uint64_t)ym * RB, s0 + (uint64_t)yp * RB};
     uint32_t co[3] = {cc, cm, cp};
     asm volatile("" : "+v"(co[0]), "+v"(co[1]), "+v"(co[2]));
@@ -428,14 +431,14 @@ __device__ __forceinline__ int node9_row(typename Form<ST>::C (&f)[9], int x, in
 // The cavity's lid row (uniform across the wave): every node takes the lid
 // equilibrium, which needs no loads.
 template <int ST, bool NT = false>
-__device__ __forceinline__ void push_lid(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int nx,
+__device__ __forceinline__ void push_lid(typename Form<ST>::T *__restrict__ d, int64_t P, int x, int y, int pitch,
                                          const Inst &in, const typename Form<ST>::C (&ref)[9], float scale)
 {
     using C = typename Form<ST>::C;
     C f[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) f[a] = C(in.lid[a]);
-    push9_xy<ST, NT>(d, P, x, y, nx, f, ref, scale);
+    push9_xy<ST, NT>(d, P, x, y, pitch, f, ref, scale);
 }
 
 // Wave-level status update: one atomic per wave and kind.
@@ -532,7 +535,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
     // arithmetic of older waves.
     if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(2);
     const Inst &in = a.one;
-    const int nx = in.nx, ny = in.ny;
+    const int nx = in.nx, ny = in.ny, pitch = in.pitch;
     const int64_t P = in.plane;
     int tx, ty;
     tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
@@ -551,14 +554,14 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
         const int y = __builtin_amdgcn_readfirstlane((ty * RPT + k) * BY + (int)threadIdx.y);
         if (y >= ny) break;
         if (a.bc == BC_CAVITY && y == ny - 1) {
-            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, pitch, in, ref, a.fp16_scale);
             continue;
         }
         const Nb n = neighbours(0, y, 1, ny, a.bc);  // rows only
         C f[9];
         {
             typename Form<ST>::T raw[9];
-            pull9_cols<ST, nl_mode(NT)>(src, P, y, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+            pull9_cols<ST, nl_mode(NT)>(src, P, y, n.ym, n.yp, pitch, cols.cc, cols.cm, cols.cp, raw);
             if constexpr ((NT & 8) != 0) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
@@ -566,7 +569,7 @@ void k_d2q9(const typename Form<ST>::T *__restrict__ src, typename Form<ST>::T *
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, pitch, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -579,7 +582,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // window [x0 - 1, x0 + BX] that the row's nodes pull from (row shifted by the
 // plane's vertical velocity, columns by at most one) in LDS: the aligned
 // BX-wide middle with 16-byte vector loads when every row start is 16-byte
-// aligned (nx a multiple of the vector width), element by element otherwise,
+// aligned (the row pitch a multiple of the vector width), element by element otherwise,
 // and the two edge columns by single loads.  Window columns outside the
 // lattice hold the wrap/clamp source of the edge nodes, so every node reads
 // exactly what the direct forms read and results are bitwise equal.
@@ -595,7 +598,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
     constexpr int W = BX + 2 * V;
     __shared__ __align__(16) T win[9][W];
     const Inst &in = a.one;
-    const int nx = in.nx, ny = in.ny;
+    const int nx = in.nx, ny = in.ny, pitch = in.pitch;
     const int64_t P = in.plane;
     const bool xw = a.bc == BC_PERIODIC;
     int tx, ty;
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
     const int x = x0 + t;
     const bool xin = x < nx;
     const int xs = xin ? x : nx - 1;
-    const bool vec = (nx % V) == 0;
+    const bool vec = (pitch % V) == 0;
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     int bad = kNoNode;
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
         const int y = ty * RY + r;  // uniform across the block
         if (y >= ny) break;
         if (a.bc == BC_CAVITY && y == ny - 1) {
-            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, pitch, in, ref, a.fp16_scale);
             continue;
         }
         const Nb n = neighbours(0, y, 1, ny, a.bc);  // rows only
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
             const int q = i / (BX / V), k = i - q * (BX / V);
             const int vy = cy9(q);
             const int ys = vy > 0 ? n.ym : (vy < 0 ? n.yp : y);
-            const T *row = src + (int64_t)q * P + (int64_t)ys * nx;
+            const T *row = src + (int64_t)q * P + (int64_t)ys * pitch;
             const int c0 = x0 + k * V;
             if (vec && c0 + V <= nx) {
                 const u32x4 *p = (const u32x4 *)(row + c0);
@@ -646,7 +649,8 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
             const int ys = vy > 0 ? n.ym : (vy < 0 ? n.yp : y);
             const int c = (t & 1) ? x0 + BX : x0 - 1;
             const int ce = c < 0 ? (xw ? nx - 1 : 0) : (c >= nx ? ((c == nx && xw) ? 0 : nx - 1) : c);
-            win[q][(t & 1) ? V + BX : V - 1] = ldraw<T, (NT & 1) != 0>(src + (int64_t)q * P + (int64_t)ys * nx + ce);
+            win[q][(t & 1) ? V + BX : V - 1] =
+                ldraw<T, (NT & 1) != 0>(src + (int64_t)q * P + (int64_t)ys * pitch + ce);
         }
         __syncthreads();
         C f[9];
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(BX) void k_d2q9_stage(const typename Form<ST>::T *_
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, pitch, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -672,7 +676,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     using C = typename Form<ST>::C;
     using T = typename Form<ST>::T;
     const Inst &in = a.one;
-    const int nx = in.nx, ny = in.ny;
+    const int nx = in.nx, ny = in.ny, pitch = in.pitch;
     const int64_t P = in.plane;
     int tx, ty;
     tile_of_block(a.xcd_swizzle, a.tiles_x, tx, ty);
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
     T raw[9];
     {
         const Nb n = neighbours(0, y0, 1, ny, a.bc);  // rows only
-        pull9_cols<ST, nl_mode(NT)>(src, P, y0, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+        pull9_cols<ST, nl_mode(NT)>(src, P, y0, n.ym, n.yp, pitch, cols.cc, cols.cm, cols.cp, raw);
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -699,16 +703,16 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
         for (int q = 0; q < 9; ++q) f[q] = load<ST>(&raw[q], ref[q], a.fp16_iscale);
         if (k + 1 < RPT && y + 1 < ny) {
             const Nb n = neighbours(0, y + 1, 1, ny, a.bc);  // rows only
-            pull9_cols<ST, nl_mode(NT)>(src, P, y + 1, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, raw);
+            pull9_cols<ST, nl_mode(NT)>(src, P, y + 1, n.ym, n.yp, pitch, cols.cc, cols.cm, cols.cp, raw);
         }
         if (a.bc == BC_CAVITY && y == ny - 1) {
-            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, pitch, in, ref, a.fp16_scale);
             continue;
         }
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         if (xin && (fl & 1)) bad = min(bad, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, pitch, f, ref, a.fp16_scale);
     }
     report(a.status, bad, guarded, a.step, a.step_base);
 }
@@ -844,7 +848,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
     // batch's tile table (instance, tile index within the instance).
     const int ii = BATCH ? a.tile_inst[tile] : 0;
     const Inst &in = BATCH ? a.inst[ii] : a.one;
-    const int nx = in.nx, ny = in.ny;
+    const int nx = in.nx, ny = in.ny, pitch = in.pitch;
     const int64_t P = in.plane;
     const int tiles_x = BATCH ? (nx + BX - 1) / BX : a.tiles_x;
     int tx, ty;
@@ -893,7 +897,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
     }
     if (kdo <= 0) {
         if (xin)
-            for (int r = 0; r < hn; ++r) carry_node(src, dst, P, 9, (y0 + r) * nx + x);
+            for (int r = 0; r < hn; ++r) carry_node(src, dst, P, 9, (y0 + r) * pitch + x);
         return;
     }
     const Cols cols = columns(xs, tx == 0 || tx == tiles_x - 1, nx, a.bc, sizeof(T));
@@ -908,7 +912,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         const int gy = row_of(j);
         if (cavity && gy == ny - 1) return;  // the lid row loads nothing
         const Nb n = neighbours(0, gy, 1, ny, a.bc);  // rows only
-        pull9_row_u<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, nx, cols.cc, cols.cm, cols.cp, r);
+        pull9_row_u<ST, nl_mode(NT)>(src, P, gy, n.ym, n.yp, pitch, cols.cc, cols.cm, cols.cp, r);
     };
     T raw[9];
     if (wave_on) pull_row(0, raw);
@@ -920,7 +924,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         const int gy = row_of(j);
         C f[9];
         const Nb n = neighbours(gx, gy, nx, ny, a.bc);
-        pull9<ST>(src, P, gx, gy, nx, n, ref, a.fp16_iscale, f);
+        pull9<ST>(src, P, gx, gy, pitch, n, ref, a.fp16_iscale, f);
         (void)node9<ST, CO>(f, role9(gx, gy, nx, ny, a.bc), in);
         T *h = halo + (j * 2 + side) * 9;
 #pragma unroll
@@ -983,7 +987,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
             const bool own = j >= 1 && j <= hn && xin;
             if (own && (fl & 1)) bad1 = min(bad1, gy * nx + x);
             guarded += __popcll(__ballot(own && (fl & 2)));
-            if (kdo == 1 && own) push9_xy_st<ST, (NT & 2) != 0>(dst, P, x, gy, nx, sv);
+            if (kdo == 1 && own) push9_xy_st<ST, (NT & 2) != 0>(dst, P, x, gy, pitch, sv);
             if constexpr (RS != 0) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) plane(q, j)[t + 1] = sv[q];
@@ -1020,7 +1024,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         // t + 2 its neighbour columns.
         const int y = y0 + j - 2;
         if (cavity && y == ny - 1) {
-            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, nx, in, ref, a.fp16_scale);
+            if (xin) push_lid<ST, (NT & 2) != 0>(dst, P, x, y, pitch, in, ref, a.fp16_scale);
             continue;
         }
         C f[9];
@@ -1042,7 +1046,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         const int fl = node9_row<ST, CO>(f, xs, y, nx, ny, a.bc, in);
         if (xin && (fl & 1)) bad2 = min(bad2, y * nx + x);
         guarded += __popcll(__ballot(xin && (fl & 2)));
-        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, nx, f, ref, a.fp16_scale);
+        if (xin) push9_xy<ST, (NT & 2) != 0>(dst, P, x, y, pitch, f, ref, a.fp16_scale);
     }
     report(status, bad1, guarded, a.step, a.step_base);
     report(status, bad2, 0, a.step + 1, a.step_base);
@@ -1068,23 +1072,24 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     const int nodes = nx * ny;
     int node = a.tile_first[t] + (int)threadIdx.x;
     const bool valid = node < nodes;
-    if (instance_stopped(a, in)) {  // uniform across the block
-        if (valid) carry_node(src + in.offset, dst + in.offset, P, 9, node);
-        return;
-    }
     if (!valid) node = nodes - 1;
     // node -> (x, y): float estimate, exact after one correction (node < 2^24).
     int y = (int)((float)node * __builtin_amdgcn_rcpf((float)nx));
     int x = node - y * nx;
     if (x < 0) { --y; x += nx; }
     if (x >= nx) { ++y; x -= nx; }
+    constexpr uint32_t E = sizeof(typename Form<ST>::T);
+    // Byte offsets of the node's row and its rows below and above (rows are
+    // `pitch` elements apart; the neighbours are one row away unless the
+    // wrap/clamp rule applies).
+    const uint32_t rb = (uint32_t)in.pitch * E, rc = (uint32_t)y * rb;
+    if (instance_stopped(a, in)) {  // uniform across the block
+        if (valid) carry_node(src + in.offset, dst + in.offset, P, 9, y * in.pitch + x);
+        return;
+    }
     C ref[9];
     ref9<C>(C(in.rho0), ref);
     const Nb n = neighbours(x, y, nx, ny, a.bc);
-    constexpr uint32_t E = sizeof(typename Form<ST>::T);
-    // Row byte offsets without multiplies: y*nx is node - x, and the rows
-    // below and above are one row away unless the wrap/clamp rule applies.
-    const uint32_t rc = (uint32_t)(node - x) * E, rb = (uint32_t)nx * E;
     const uint32_t rm = n.ym == y - 1 ? rc - rb : (uint32_t)n.ym * rb;
     const uint32_t rp = n.yp == y + 1 ? rc + rb : (uint32_t)n.yp * rb;
     C f[9];
@@ -1099,7 +1104,8 @@ __global__ __launch_bounds__(BLK) void k_d2q9_batch(const typename Form<ST>::T *
     const int role = role9(x, y, nx, ny, a.bc);
     const int fl = node9<ST, CO>(f, role, in);
     if (valid)
-        push9_inst<ST, (NT & 2) != 0>(uniform_addr(dst + in.offset), P, (uint32_t)node * E, f, ref, a.fp16_scale);
+        push9_inst<ST, (NT & 2) != 0>(uniform_addr(dst + in.offset), P, rc + (uint32_t)x * E, f, ref,
+                                      a.fp16_scale);
     const int guarded = __popcll(__ballot(valid && (fl & 2)));
     report(a.status + i, valid && (fl & 1) ? node : kNoNode, guarded, a.step, a.step_base);
 }
@@ -1128,9 +1134,11 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
     T *L0 = (T *)lds_raw;
     T *L1 = L0 + 9 * nodes;
     const T *g = src + in.offset;
+    // LDS holds the nodes without the row padding: node j of plane q at
+    // q * nodes + j.
     for (int idx = threadIdx.x; idx < 9 * nodes; idx += blockDim.x) {
-        const int q = idx / nodes, j = idx - q * nodes;
-        L0[idx] = g[q * in.plane + j];
+        const int q = idx / nodes, j = idx - q * nodes, jy = j / nx;
+        L0[idx] = g[q * in.plane + jy * in.pitch + (j - jy * nx)];
     }
     __syncthreads();
     C ref[9];
@@ -1164,8 +1172,8 @@ __global__ __launch_bounds__(1024) void k_d2q9_lds(const typename Form<ST>::T *s
     const T *fin = (kdone & 1) ? L1 : L0;
     T *o = dst + in.offset;
     for (int idx = threadIdx.x; idx < 9 * nodes; idx += blockDim.x) {
-        const int q = idx / nodes, j = idx - q * nodes;
-        o[q * in.plane + j] = fin[idx];
+        const int q = idx / nodes, j = idx - q * nodes, jy = j / nx;
+        o[q * in.plane + jy * in.pitch + (j - jy * nx)] = fin[idx];
     }
     // Status: rare events, one atomic per reporting lane.
     DevStatus *st = a.status + i;
@@ -1468,7 +1476,7 @@ __global__ void k_init(Inst in, int bc, const double *__restrict__ rho, const do
         } else {
             ref = (a == 0 ? C(2.0 / 3.0) : C(1.0 / 6.0)) * C(in.rho0);
         }
-        store<ST>(d + (int64_t)a * in.plane + i, C(v), ref, scale);
+        store<ST>(d + (int64_t)a * in.plane + (int64_t)y * in.pitch + x, C(v), ref, scale);
     }
 }
 
@@ -1482,13 +1490,14 @@ __global__ void k_gather(Inst in, int bc, const typename Form<ST>::T *__restrict
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int x = i % nx, y = i / nx;
+    const int pitch = in.pitch;
     const typename Form<ST>::T *s = buf + in.offset;
     double f[9];
     if (B == 9) {
         C ref[9];
         ref9<C>(C(in.rho0), ref);
         C g[9];
-        pull9<ST>(s, in.plane, x, y, nx, neighbours(x, y, nx, ny, bc), ref, iscale, g);
+        pull9<ST>(s, in.plane, x, y, pitch, neighbours(x, y, nx, ny, bc), ref, iscale, g);
         for (int a = 0; a < 9; ++a) f[a] = double(g[a]);
     } else {
         const bool wrap = bc == BC_PERIODIC;

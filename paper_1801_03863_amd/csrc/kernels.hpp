@@ -21,9 +21,12 @@ struct DevStatus {
 
 // One lattice instance as the kernels see it.  Populations of instance i
 // live in b planes of `plane` elements starting at element `offset` of each
-// of the two buffers; node (x, y) is element y*nx + x of a plane.
+// of the two buffers; node (x, y) is element y*pitch + x of a plane (D2Q9
+// rows start on whole 128-byte lines; elements x >= nx of a row are padding
+// that no kernel reads).  Node numbers (status, host fields) stay y*nx + x.
 struct Inst {
     int32_t nx, ny;
+    int32_t pitch;   // row stride in elements (>= nx)
     int64_t offset;
     int64_t plane;
     double omega;    // 1/tau

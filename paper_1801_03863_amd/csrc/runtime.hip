@@ -55,6 +55,11 @@ constexpr int32_t kPadMaxBytes = 8192;
 constexpr int32_t kPadDefaultBytes = 2048;
 constexpr int32_t kPadCandidates[] = {0, 1024, 2048, 4096, 8192};
 constexpr int64_t kMaxBatchNodes = int64_t(1) << 22;
+// D2Q9 rows are stored at a pitch of whole lines of this many bytes, so every
+// row's first element starts a cache line: a row read by a wave then touches
+// the fewest lines, and row writes fill whole lines.  Lattices of arbitrary
+// width (a batch's instances) would otherwise start most rows mid-line.
+constexpr int64_t kRowLineBytes = 128;
 
 size_t elem_bytes(int precision)
 {
@@ -77,6 +82,15 @@ int storage_of(int precision)
     }
 }
 
+// Row stride of an instance in elements: D2Q9 rows rounded up to whole
+// lines of kRowLineBytes; a D1Q3 lattice is one row.
+int64_t row_pitch(const lbm_params_t &q)
+{
+    if (q.lattice == LBM_D1Q3) return q.nx;
+    const int64_t line = kRowLineBytes / (int64_t)elem_bytes(q.precision);
+    return ((int64_t)q.nx + line - 1) / line * line;
+}
+
 int check_params(const lbm_params_t *p)
 {
     if (!p) return fail(LBM_EINVAL, "null parameters");
@@ -89,6 +103,9 @@ int check_params(const lbm_params_t *p)
     if (p->lattice == LBM_D1Q3 && p->ny != 1) return fail(LBM_EINVAL, "ny must be 1 for D1Q3");
     if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)0x7fffffff / 2)
         return fail(LBM_EINVAL, "lattice too large for one instance (nx*ny must be < 2^30)");
+    if (p->lattice == LBM_D2Q9 && row_pitch(*p) * (int64_t)p->ny > (int64_t)0x7fffffff)
+        return fail(LBM_EINVAL, "lattice too large for one instance (its rows, stored at a pitch of whole "
+                                "128-byte lines, must hold fewer than 2^31 elements)");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be finite and > 1/2");
     if (p->tau2 > 0.0 && !(p->tau2 > 0.5 && std::isfinite(p->tau2)))
         return fail(LBM_EINVAL, "tau2 must be finite and > 1/2 (or <= 0 for the default)");
@@ -160,8 +177,8 @@ namespace {
 // Whether a single lattice of these parameters takes a plane pad.
 bool paddable(const lbm_params_t &q, int batch)
 {
-    const int64_t nodes = (int64_t)q.nx * (q.lattice == LBM_D1Q3 ? 1 : q.ny);
-    return !batch && round_up(nodes, kAlignElems) * (int64_t)elem_bytes(q.precision) >= kPadMinPlaneBytes;
+    const int64_t elems = row_pitch(q) * (q.lattice == LBM_D1Q3 ? 1 : q.ny);
+    return !batch && round_up(elems, kAlignElems) * (int64_t)elem_bytes(q.precision) >= kPadMinPlaneBytes;
 }
 
 int layout(const lbm_params_t *p, int32_t n, int batch, int b, std::vector<Inst> *inst, int64_t *elems,
@@ -173,9 +190,10 @@ int layout(const lbm_params_t *p, int32_t n, int batch, int b, std::vector<Inst>
         Inst in{};
         in.nx = q.nx;
         in.ny = q.lattice == LBM_D1Q3 ? 1 : q.ny;
+        in.pitch = (int32_t)row_pitch(q);
         in.offset = off;
         in.stop = INT64_MAX;
-        in.plane = round_up((int64_t)in.nx * in.ny, kAlignElems);
+        in.plane = round_up((int64_t)in.pitch * in.ny, kAlignElems);
         int64_t room = in.plane;  // elements reserved per plane
         if (paddable(q, batch)) {
             const int64_t eb = (int64_t)elem_bytes(q.precision);
@@ -272,7 +290,7 @@ int set_pad(lbm_ctx *c, int32_t pad)
     const int64_t eb = (int64_t)c->elem;
     const int64_t old_plane = c->inst[0].plane;
     const int64_t new_plane = c->plane_base + pad / eb;
-    const size_t width = (size_t)c->inst[0].nx * (size_t)c->inst[0].ny * (size_t)eb;
+    const size_t width = (size_t)c->inst[0].pitch * (size_t)c->inst[0].ny * (size_t)eb;
     const char *src = c->buf[c->cur];
     char *dst = c->buf[c->cur ^ 1];
     for (int q = 0; q < c->b; ++q)
@@ -477,7 +495,7 @@ int create(const lbm_params_t *p, int32_t n, int batch, const double *rho, const
     layout(p, n, batch, c->b, &c->inst, &c->elems, &c->nodes);
     if (paddable(p[0], batch)) {
         c->pad = kPadDefaultBytes;
-        c->plane_base = round_up((int64_t)c->inst[0].nx * c->inst[0].ny, kAlignElems);
+        c->plane_base = round_up((int64_t)c->inst[0].pitch * c->inst[0].ny, kAlignElems);
     }
     int64_t acc = 0;
     for (int i = 0; i < n; ++i) {

@@ -60,9 +60,16 @@ def test_invalid_parameters_rejected_before_device_work(B, bad):
 
 
 def test_workspace_size_formula(B):
-    p = B.make_params("d2q9", "minxent4", "cavity", "fp32", 100, 50, 0.6)
-    plane = (100 * 50 + 63) // 64 * 64
-    assert B.lbm_workspace_bytes(p) == 2 * ((9 * plane * 4 + 255) // 256 * 256)
+    # D2Q9 rows are stored at a pitch of whole 128-byte lines: 100 FP32
+    # values take 128 elements, 100 FP64 values 112, 100 FP16 values 128.
+    for prec, eb, pitch in (("fp32", 4, 128), ("fp64", 8, 112), ("fp16dev", 2, 128), ("fp32_newton64", 4, 128)):
+        p = B.make_params("d2q9", "minxent4", "cavity", prec, 100, 50, 0.6)
+        plane = (pitch * 50 + 63) // 64 * 64
+        assert B.lbm_workspace_bytes(p) == 2 * ((9 * plane * eb + 255) // 256 * 256), prec
+    # Rows already a whole number of lines keep their width.
+    p = B.make_params("d2q9", "minxent4", "cavity", "fp32", 96, 50, 0.6)
+    assert B.lbm_workspace_bytes(p) == 2 * ((9 * 96 * 50 * 4 + 255) // 256 * 256)
+    # A D1Q3 lattice is one row: no pitch.
     q = B.make_params("d1q3", "srt", "tube", "fp16dev", 1000, 1, 0.6)
     assert B.lbm_workspace_bytes(q) == 2 * ((3 * 1024 * 2 + 255) // 256 * 256)
 
@@ -106,8 +113,16 @@ def test_lattice_size_limit(B):
         B.lbm_workspace_bytes(big)
     assert ei.value.code == B.LBM_EINVAL
     ok = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 32767, 32768, 0.6)
-    plane = (32767 * 32768 + 63) // 64 * 64 + 8192 // 2
+    plane = 32768 * 32768 + 8192 // 2  # rows padded to 32768 FP16 values
     assert B.lbm_workspace_bytes(ok) == 2 * ((9 * plane * 2 + 255) // 256 * 256)
+    # The padded rows must also hold fewer than 2^31 elements: a 3-wide FP16
+    # lattice stores 64 values per row.
+    thin = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 3, 1 << 25, 0.6)
+    with pytest.raises(B.LbmError) as ei:
+        B.lbm_workspace_bytes(thin)
+    assert ei.value.code == B.LBM_EINVAL
+    thin_ok = B.make_params("d2q9", "minxent4", "cavity", "fp16dev", 3, (1 << 25) - 1, 0.6)
+    assert B.lbm_workspace_bytes(thin_ok) > 0
 
 
 def test_batch_needs_an_instance(B):
