@@ -826,7 +826,8 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
     // (The wave index is read from the first lane so that the compiler knows
     // it, and everything derived from the tile, to be wave-uniform.)
     const int wave = WT > 0 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
-    const int tile = WT > 0 ? (int)blockIdx.x * WT + wave : (int)blockIdx.x;
+    const int tile = WT > 0 ? (int)blockIdx.x * WT + wave
+                            : (BATCH && a.xcd_swizzle ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
     if constexpr (WT > 0) {
         if (tile >= a.ntiles) return;  // wave-uniform; no block barrier in this mode
     }
@@ -1967,9 +1968,17 @@ hipError_t prep9bt2w()
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
 }
 
+// Two-step batch shapes 17-20 are 9, 14, 15 and 10 with the tile table read
+// in XCD-banded order: block b takes the tile xcd_remap(b), so each XCD works
+// through a contiguous band of the table and horizontally adjacent tiles (and,
+// in narrow instances, vertically adjacent ones) share its L2, which serves
+// the window lines they have in common.
+constexpr int banded_base(int v) { return v == 17 ? 9 : v == 18 ? 14 : v == 19 ? 15 : v == 20 ? 10 : v; }
+
 template <int ST, int CO>
 hipError_t dispatch9bt2(int v, bool prep, const void *src, void *dst, const StepArgs &a, hipStream_t s)
 {
+    v = banded_base(v);
 #define LBM_BT2W(H, RS, NT, WT) return prep ? prep9bt2w<ST, CO, H, RS, NT, WT>() : go9bt2w<ST, CO, H, RS, NT, WT>(src, dst, a, s)
     switch (v) {
     case 12: LBM_BT2W(16, 3, 6, 4);
@@ -1998,12 +2007,17 @@ hipError_t dispatch9b(int v, const void *src, void *dst, const StepArgs &a_in, h
 {
     using T = typename Form<ST>::T;
     // Tiles run in launch order; shapes 5 and 6 are 3 and 4 with tiles in
-    // XCD-banded order instead (measured slower, kept as candidates).
+    // XCD-banded order instead (measured slower, kept as candidates), and so
+    // are the two-step shapes 17-20 (of 9, 14, 15 and 10).
     StepArgs a = a_in;
     a.xcd_swizzle = 0;
     if (v == 5 || v == 6) {
         a.xcd_swizzle = 1;
         v -= 2;
+    }
+    if (banded_base(v) != v) {
+        a.xcd_swizzle = 1;
+        v = banded_base(v);
     }
     switch (v) {
     case 0: hipLaunchKernelGGL((k_d2q9_batch<ST, CO, 256, 0>), dim3(a.ntiles), dim3(256), 0, s, (const T *)src, (T *)dst, a); break;
@@ -2157,7 +2171,12 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {64, 1, "batch two steps per launch, 64x16 tiles one per wave (4 waves/block), split rings, nt-load(unshifted planes) nt-store", 2, 16},
                                 {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
                                 {256, 1, "batch two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2, 16},
-                                {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2, 16}};
+                                {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store waves>=5", 2, 16},
+                                // 9, 14, 15 and 10 with tiles in XCD-banded order
+                                {64, 1, "batch two steps per launch, 64x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
+                                {256, 1, "batch two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
+                                {64, 1, "batch two steps per launch, 64x16 tiles, split rings, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16}};
 // Single-step batch shapes (every collision rule); the rest of kShapesB9 are
 // two-step shapes of MinxEnt4.
 constexpr int kNumB9One = 9;
