@@ -1996,6 +1996,8 @@ hipError_t dispatch9bt2(int v, bool prep, const void *src, void *dst, const Step
     case 14: LBM_BT2(256, 16, 3, 6);
     case 15: LBM_BT2(256, 16, 0, 6);
     case 16: LBM_BT2B(256, 16, 3, 6, 5);
+    case 21: LBM_BT2(128, 16, 3, 6);
+    case 22: LBM_BT2(128, 16, 0, 6);
     default: return hipErrorInvalidValue;
     }
 #undef LBM_BT2
@@ -2176,7 +2178,9 @@ constexpr ShapeB kShapesB9[] = {{256, 1, "batch 256 nodes/block"}, {128, 1, "bat
                                 {64, 1, "batch two steps per launch, 64x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
                                 {256, 1, "batch two steps per launch, 256x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
                                 {256, 1, "batch two steps per launch, 256x16 tiles, split rings, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
-                                {64, 1, "batch two steps per launch, 64x16 tiles, split rings, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16}};
+                                {64, 1, "batch two steps per launch, 64x16 tiles, split rings, nt-load(unshifted planes) nt-store, XCD-banded", 2, 16},
+                                {128, 1, "batch two steps per launch, 128x16 tiles, 3-row ring, nt-load(unshifted planes) nt-store", 2, 16},
+                                {128, 1, "batch two steps per launch, 128x16 tiles, split rings, nt-load(unshifted planes) nt-store", 2, 16}};
 // Single-step batch shapes (every collision rule); the rest of kShapesB9 are
 // two-step shapes of MinxEnt4.
 constexpr int kNumB9One = 9;
