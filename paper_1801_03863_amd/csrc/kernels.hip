@@ -746,7 +746,9 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 // That is 18 plane-rows of LDS instead of 36, with one barrier per row.  The
 // two halo columns of every window row are computed first, by the first
 // 2 (H + 2) threads, into their own LDS array, and copied into the ring as
-// each row is written.  Each first-step row's loads are
+// each row is written.  The second step reads a halo column only in the three
+// planes that stream in from that side (1, 5, 8 from the left; 3, 6, 7 from
+// the right), so the array keeps those six values per row.  Each first-step row's loads are
 // issued one iteration ahead, before the barrier, and complete during the
 // second step of the row before.
 // Only nodes inside the tile report status (first step at a.step, second at
@@ -757,11 +759,20 @@ __global__ __launch_bounds__(BX) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WP
 constexpr int t2_plane_rows(int rs) { return rs == 0 ? 18 : 9 * rs; }
 
 // LDS of the two-step kernel: the ring (plane-rows of bx + 2 columns) and
-// the nine planes of the halo columns of every window row.
+// the three planes the second step reads in each halo column of every window
+// row.
 template <class T>
 constexpr size_t t2_lds_bytes(int bx, int h, int rs)
 {
-    return sizeof(T) * (size_t)(t2_plane_rows(rs) * (bx + 2) + 18 * (h + 2));
+    return sizeof(T) * (size_t)(t2_plane_rows(rs) * (bx + 2) + 6 * (h + 2));
+}
+
+// Plane of the k-th value (k < 3) kept for a halo column: the left column
+// (side 0) feeds planes 1, 5 and 8 of the tile's first column, the right one
+// planes 3, 6 and 7 of its last.
+__device__ __forceinline__ int t2_halo_plane(int side, int k)
+{
+    return side ? (k == 0 ? 3 : (k == 1 ? 6 : 7)) : (k == 0 ? 1 : (k == 1 ? 5 : 8));
 }
 
 // Lattice coordinate of window coordinate g on an axis of n nodes: the
@@ -833,7 +844,7 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
     }
     T *ring = (T *)(t2_lds + (size_t)wave * (WT > 0 ? t2_wave_lds_bytes<T>(H, RS) : 0));
     // RS > 0: [RS][9][W]; RS = 0: planes 7,8 [2][2][W], 1,3 [3][2][W], 5,6 [4][2][W]
-    T *halo = ring + t2_plane_rows(RS) * W;  // [H + 2][2][9]
+    T *halo = ring + t2_plane_rows(RS) * W;  // [H + 2][2][3]
     // Plane q of window row j in the ring (q and the ring layout are
     // compile-time, j is uniform).
     auto plane = [&](int q, int j) -> T * {
@@ -927,9 +938,12 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
         const Nb n = neighbours(gx, gy, nx, ny, a.bc);
         pull9<ST>(src, P, gx, gy, pitch, n, ref, a.fp16_iscale, f);
         (void)node9<ST, CO>(f, role9(gx, gy, nx, ny, a.bc), in);
-        T *h = halo + (j * 2 + side) * 9;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) store<ST>(h + q, f[q], ref[q], a.fp16_scale);
+        // The three planes the second step reads in this column (t2_halo_plane;
+        // ref is the same within the axis and within the diagonal directions).
+        T *h = halo + (j * 2 + side) * 3;
+        store<ST>(h + 0, side ? f[3] : f[1], ref[1], a.fp16_scale);
+        store<ST>(h + 1, side ? f[6] : f[5], ref[5], a.fp16_scale);
+        store<ST>(h + 2, side ? f[7] : f[8], ref[5], a.fp16_scale);
     }
 
     int bad1 = kNoNode, bad2 = kNoNode;
@@ -992,9 +1006,9 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
             if constexpr (RS != 0) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) plane(q, j)[t + 1] = sv[q];
-                if (t < 18) {
-                    const int side = t >= 9, q = t - 9 * side;
-                    plane(q, j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                if (t < 6) {
+                    const int side = t >= 3, k = t - 3 * side;
+                    plane(t2_halo_plane(side, k), j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 3 + k];
                 }
             } else {
 #pragma unroll
@@ -1005,9 +1019,9 @@ void k_d2q9_t2(const typename Form<ST>::T *__restrict__ src_all, typename Form<S
                 v0 = sv[0];
                 v2 = sv[2];
                 v4 = sv[4];
-                if (t < 12) {
-                    const int side = t >= 6, q = kShifted[t - 6 * side];
-                    plane(q, j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 9 + q];
+                if (t < 6) {
+                    const int side = t >= 3, k = t - 3 * side;
+                    plane(t2_halo_plane(side, k), j)[side ? tw + 1 : 0] = halo[(j * 2 + side) * 3 + k];
                 }
             }
         }

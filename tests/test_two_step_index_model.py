@@ -90,6 +90,12 @@ def ring_slot(rs, q, j):
     return ("C", j % 4, q - 5)
 
 
+# Planes the second step reads in the left (x0 - 1) and right (x0 + tw) halo
+# columns: those whose velocity points right, and left.
+HALO_LEFT = (1, 5, 8)
+HALO_RIGHT = (3, 6, 7)
+
+
 def two_steps(f, nx, ny, bc, bx, h, rs, wave=None):
     """wave: None for tiles of bx columns; else the batch kernel's balanced
     tiles, wave lanes to a wave: the instance's columns spread evenly over
@@ -150,8 +156,13 @@ def two_steps(f, nx, ny, bc, bx, h, rs, wave=None):
                 for q in written:
                     row = write(q, j)
                     row[1:bx + 1] = v[q]
-                    row[0] = halo[j, 0, q]
-                    row[tw + 1] = halo[j, 1, q]
+                    # the kernel keeps a halo column only in the planes that
+                    # stream in from its side; the others stay unwritten
+                    # (NaN), so a read of one would fail the check below
+                    if q in HALO_LEFT:
+                        row[0] = halo[j, 0, q]
+                    if q in HALO_RIGHT:
+                        row[tw + 1] = halo[j, 1, q]
                 s0, s2 = u0, u2b
                 u0, u2b, u2a = v[0].copy(), u2a, v[2].copy()
                 if j < 2:
