@@ -383,6 +383,29 @@ __device__ __forceinline__ int node9(typename Form<ST>::C (&f)[9], int role, con
         for (int a = 0; a < 9; ++a) f[a] = C(in.lid[a]);
         return 0;
     }
+    if constexpr (ST == ST_F16DEV && (CO == CO_MINXENT4 || CO == CO_MINXENT2)) {
+        // FP16 deviations: the collision runs on the fluid lanes only, then
+        // the wall lanes, whose f still holds the pulled populations, swap
+        // them.  The same results as the order below; in this form the
+        // compiler then keeps fewer values live across the collision (69
+        // instead of 77 VGPRs in the tuned two-step shape, 7 waves per SIMD
+        // instead of 6).  In the double-precision forms this order costs
+        // registers instead.
+        int r = 0;
+        if (role != R_WALL) {
+            bool ok = true;
+            const bool g = collide_minxent<C, CO == CO_MINXENT2, true, false>(f, C(in.omega), C(in.omega2), ok);
+            r = (g ? 2 : 0) | (ok ? 0 : 1);
+        }
+        if (role == R_WALL) {
+            C t;
+            t = f[1]; f[1] = f[3]; f[3] = t;
+            t = f[2]; f[2] = f[4]; f[4] = t;
+            t = f[5]; f[5] = f[7]; f[7] = t;
+            t = f[6]; f[6] = f[8]; f[8] = t;
+        }
+        return r;
+    }
     if (role == R_WALL) {
         C t;
         t = f[1]; f[1] = f[3]; f[3] = t;
