@@ -398,18 +398,22 @@ def test_copy_kernel(nbytes):
 # Plane pad (single lattices with planes of at least 1 MiB)
 # --------------------------------------------------------------------------
 
-def test_plane_pad_moves_the_state_bitwise():
-    # 1024 x 300 FP32: 1.2 MB planes, so the context takes a pad.  Pads
+@pytest.mark.parametrize("nx", [1024, 1000])
+def test_plane_pad_moves_the_state_bitwise(nx):
+    # nx x 300 FP32: 1.2 MB planes, so the context takes a pad.  Pads
     # changed mid-run (with graph replay around them) leave the trajectory
-    # bitwise equal to a run that keeps the default pad.
-    nx, ny = 1024, 300
+    # bitwise equal to a run that keeps the default pad.  1000 columns are
+    # stored at a pitch of 1024 (whole 128-byte lines), and the move copies
+    # the padded rows.
+    ny = 300
+    pitch = (nx + 31) // 32 * 32
     rho, ux, uy = smooth_fields(nx, ny, seed=31)
     b = B()
     p = b.make_params("d2q9", "minxent4", "cavity", "fp32", nx, ny, 0.6, 0.0, 0.1, 1.0)
     ref = b.lbm_init(p, rho, ux, uy)
     c = b.lbm_init(p, rho, ux, uy)
     try:
-        base = (nx * ny + 63) // 64 * 64
+        base = (pitch * ny + 63) // 64 * 64
         assert b.lbm_get_layout(c) == (base + 2048 // 4, 2048)
         b.lbm_step(ref, 25)
         b.lbm_set_graph_chunk(c, 4)
