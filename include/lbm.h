@@ -270,7 +270,8 @@ void lbm_free(lbm_ctx_t *ctx);
  *   hip_stream:    hipStream_t as void*, NULL for the default stream.
  * Results are bitwise those of lbm_init + lbm_step + lbm_moments with the
  * same parameters.  A lattice needing more than LBM_NOALLOC_SCRATCH_BYTES
- * (256 + 2 * b * round_up(nx*ny, 64) * bytes per population) is rejected
+ * (256 + 2 * b * round_up(ny * pitch, 64) * bytes per population, each
+ * buffer rounded up to 256 bytes; pitch as in lbm_set_plane_pad) is rejected
  * with LBM_EINVAL before any work is enqueued.  Every call on one GPU shares
  * that GPU's array and leaves its state there: calls that overlap on one GPU
  * (two streams, or two threads) race and must be serialised by the caller. */

@@ -280,9 +280,10 @@ __device__ __forceinline__ uint64_t uniform_addr(const void *p)
 // Batched D2Q9: pull the nine raw populations of a node of one instance,
 // whose planes start at the block-uniform address s (stride P elements),
 // from byte offsets of rows (rc own, rm below, rp above) and columns (cc
-// own, cm left, cp right).  An instance holds fewer than 2^22 nodes, so
-// every offset fits 32 bits and each load takes the scalar-base + 32-bit
-// vector-offset form.  NL as for pull9_cols.
+// own, cm left, cp right).  An instance holds fewer than 2^22 nodes and
+// pads each row by fewer than 64 elements, so its plane spans fewer than
+// 2^28 elements (2^31 bytes) and every offset fits 32 bits: each load takes
+// the scalar-base + 32-bit vector-offset form.  NL as for pull9_cols.
 template <int ST, int NL>
 __device__ __forceinline__ void pull9_inst(uint64_t s, int64_t P, uint32_t rc, uint32_t rm, uint32_t rp,
                                            uint32_t cc, uint32_t cm, uint32_t cp, typename Form<ST>::T (&r)[9])
